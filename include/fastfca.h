@@ -1,0 +1,145 @@
+/*
+ * libfastfca -- FastFCA-AS and conventional FCA EM on one AMD Instinct MI355X
+ * (gfx950), C ABI.
+ *
+ * Method: N. Ito and T. Nakatani, "FastFCA-AS: joint diagonalization based
+ * acceleration of full-rank spatial covariance analysis for separating any
+ * number of sources" (arXiv 1805.09498).  Section numbers and equation
+ * numbers below refer to that paper.
+ *
+ * Notation.  The observed STFT mixture at I microphones is x(n,f) in C^I
+ * (the paper's y(n,f), Section 2), n = 0..N-1 frames, f = 0..F-1 bins; J
+ * sources.  The FCA model (Section 3.1, eq. 1-2) gives source image j the
+ * covariance v_j(n,f) S_j(f).  FastFCA-AS constrains
+ * S_j(f) = P(f)^-H diag(lambda_j(f)) P(f)^-1 (eq. 12).
+ *
+ * Array layouts (all row-major, C order; complex values are interleaved
+ * (re, im) float pairs, the layout of torch.complex64):
+ *   x    [F][N][I]      complex  mixture
+ *   v    [F][N][J]      float    v_j(n,f) > 0
+ *   lam  [F][J][I]      float    lambda_{j,i}(f) > 0, the diagonal of Lambda_j(f)
+ *   P    [F][I][I]      complex  P[f][r][c] = P(f)_{rc}
+ *   R    [F][J][I][I]   complex  S_j(f), Hermitian positive definite
+ *   out  [J][F][N][I]   complex  separated source images
+ *
+ * Memory: every array argument is a device pointer owned by the caller,
+ * except the host scalar of fca_loglik.  fca_init copies what it needs into
+ * library-owned device memory, so the caller may free its inputs once
+ * fca_init has returned and the stream has reached that point.  The library
+ * owns its state until fca_destroy.
+ *
+ * Streams: all work is enqueued on the hipStream_t given to fca_init and is
+ * asynchronous unless stated.  A context is not thread-safe; separate
+ * contexts are independent.
+ *
+ * Errors: every call returns an fca_status; nothing else crosses the ABI.
+ * Host-side argument checks happen before any device work is enqueued.
+ * fca_last_error gives a message for the last failure on a context (or,
+ * with NULL, for the last failed fca_init of the calling thread).
+ *
+ * Supported sizes: 1 <= I <= 8 microphones, 1 <= J <= 9 sources, N >= I
+ * frames (below that the weighted covariances of eq. 23 are singular),
+ * F >= 1 bins, N*F*max(I,J) < 2^31.
+ */
+#ifndef FASTFCA_H
+#define FASTFCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;
+} fca_c64;
+
+typedef struct fca_ctx fca_ctx;
+
+typedef enum {
+  FCA_OK = 0,
+  FCA_ERR_ARG = -1,         /* bad pointer, size or option */
+  FCA_ERR_UNSUPPORTED = -2, /* (I, J) outside the instantiated range */
+  FCA_ERR_HIP = -3,         /* a HIP runtime call failed; see fca_last_error */
+  FCA_ERR_STATE = -4,       /* call does not match the context's method */
+  FCA_ERR_NONFINITE = -5    /* non-finite parameters found (check_finite=1);
+                               this is also how a singular P(f) or weighted
+                               covariance shows up */
+} fca_status;
+
+typedef enum {
+  FCA_METHOD_AS = 0, /* FastFCA-AS: state (v, lambda, P), Section 4 */
+  FCA_METHOD_EM = 1  /* conventional FCA EM: state (v, S), Section 3.3 */
+} fca_method;
+
+/* Create a context for one mixture (Section 2: estimate the J source images
+ * from x).  x, v0, lam0 and P0 are device pointers in the layouts above.
+ *   FCA_METHOD_AS: the state is (v0, lam0, P0); R0 must be NULL.
+ *   FCA_METHOD_EM: the state is (v0, S); S = R0 when R0 is not NULL, else
+ *                  S_j(f) = P0(f)^-H diag(lam0_j(f)) P0(f)^-1 (eq. 12) is
+ *                  formed on the device, so both methods can start from the
+ *                  same point.
+ * hip_stream is a hipStream_t (NULL = the default stream).
+ * Returns FCA_ERR_ARG for NULL/misaligned pointers (8-byte alignment for
+ * complex, 4 for float) or bad sizes, FCA_ERR_UNSUPPORTED outside the
+ * (I, J) range, FCA_ERR_HIP if device allocation fails.  On failure *out is
+ * set to NULL. */
+fca_status fca_init(fca_ctx **out, fca_method method, int F, int N, int I, int J,
+                    const fca_c64 *x, const float *v0, const float *lam0,
+                    const fca_c64 *P0, const fca_c64 *R0, void *hip_stream);
+
+/* Run n_iter hybrid iterations of FastFCA-AS (Section 4.4): the EM update of
+ * v and lambda (eq. 15-20), then K fixed-point updates of every P(f) (eq. 23,
+ * K from the "K" option, default 1) with the new v and lambda.
+ * n_iter >= 0.  FCA_ERR_STATE on an EM context.  Asynchronous. */
+fca_status fastfca_as_iterate(fca_ctx *ctx, int n_iter);
+
+/* Run n_iter iterations of the conventional FCA EM algorithm (Section 3.3,
+ * eq. 6-10): per time-frequency point an I x I inverse and 2J I x I products.
+ * FCA_ERR_STATE on an AS context.  Asynchronous. */
+fca_status fca_em_iterate(fca_ctx *ctx, int n_iter);
+
+/* Multichannel Wiener filter (eq. 3) with the current parameters: for the
+ * AS method R_j(n,f) follows eq. 15.  out is a device array [J][F][N][I]
+ * complex.  The J estimates sum to x.  Asynchronous. */
+fca_status fca_wiener_separate(fca_ctx *ctx, fca_c64 *out);
+
+/* Log-likelihood of the current parameters, L1 (eq. 5) for EM contexts, L2
+ * (eq. 14) for AS contexts, including the -I ln(pi) constant of the complex
+ * normal density, summed over all N*F points.  out is a HOST pointer.
+ * Synchronises the context's stream. */
+fca_status fca_loglik(fca_ctx *ctx, double *out);
+
+/* Copy the current parameters to caller-owned device arrays in the ABI
+ * layouts.  AS: v [F][N][J], lam [F][J][I], P_or_R = P [F][I][I].
+ * EM: v [F][N][J], lam ignored (may be NULL), P_or_R = S [F][J][I][I].
+ * Any pointer may be NULL to skip it.  Asynchronous. */
+fca_status fca_get_params(fca_ctx *ctx, float *v, float *lam, fca_c64 *P_or_R);
+
+/* Overwrite the current parameters from device arrays in the same layouts
+ * as fca_get_params (NULL skips).  Asynchronous. */
+fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
+                          const fca_c64 *P_or_R);
+
+/* Options: "K" (fixed-point steps per hybrid iteration, 1..64, default 1),
+ * "check_finite" (0/1: after each iterate call, synchronise and return
+ * FCA_ERR_NONFINITE if a parameter is NaN/Inf), "path" (0 = automatic,
+ * 1 = force the frequency-resident kernels, 2 = force the streaming
+ * kernels), "waves" (64-lane waves per workgroup of the frequency-resident
+ * kernel: 0 = automatic, 1, 2 or 4).  Unknown keys or values out of range
+ * give FCA_ERR_ARG. */
+fca_status fca_set_option(fca_ctx *ctx, const char *key, long long value);
+
+/* Human-readable message for the last error on ctx, or for the calling
+ * thread's last failed fca_init when ctx is NULL.  Never NULL. */
+const char *fca_last_error(const fca_ctx *ctx);
+
+/* Release all device memory of the context (after synchronising its stream).
+ * NULL is ignored. */
+void fca_destroy(fca_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTFCA_H */

@@ -1,0 +1,338 @@
+// C ABI of libfastfca (declared in include/fastfca.h): argument checks,
+// context and device-memory ownership, dispatch to the (I, J) kernel sets.
+#include "fastfca.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fca_state.h"
+
+namespace fca {
+#define FCA_DECL_J(I_, J_) const KernelSet* kernel_set_I##I_##_J##J_();
+#define FCA_DECL_I(I_)                                                                     \
+  FCA_DECL_J(I_, 1) FCA_DECL_J(I_, 2) FCA_DECL_J(I_, 3) FCA_DECL_J(I_, 4) FCA_DECL_J(I_, 5) \
+  FCA_DECL_J(I_, 6) FCA_DECL_J(I_, 7) FCA_DECL_J(I_, 8) FCA_DECL_J(I_, 9)
+FCA_DECL_I(1) FCA_DECL_I(2) FCA_DECL_I(3) FCA_DECL_I(4)
+FCA_DECL_I(5) FCA_DECL_I(6) FCA_DECL_I(7) FCA_DECL_I(8)
+
+const KernelSet* kernel_set(int I, int J) {
+#define FCA_ROW(I_)                                                                         \
+  { &kernel_set_I##I_##_J1, &kernel_set_I##I_##_J2, &kernel_set_I##I_##_J3,                 \
+    &kernel_set_I##I_##_J4, &kernel_set_I##I_##_J5, &kernel_set_I##I_##_J6,                 \
+    &kernel_set_I##I_##_J7, &kernel_set_I##I_##_J8, &kernel_set_I##I_##_J9 }
+  static const KernelSet* (*const table[8][9])() = {FCA_ROW(1), FCA_ROW(2), FCA_ROW(3), FCA_ROW(4),
+                                                    FCA_ROW(5), FCA_ROW(6), FCA_ROW(7), FCA_ROW(8)};
+  if (I < 1 || I > 8 || J < 1 || J > 9) return nullptr;
+  return table[I - 1][J - 1]();
+}
+}  // namespace fca
+
+using fca::DevState;
+using fca::KernelSet;
+
+struct fca_ctx {
+  fca_method method;
+  int F, N, I, J;
+  hipStream_t stream;
+  const KernelSet* ks;
+  DevState s;
+  void* arena;
+  int check_finite;
+  int path;   // 0 auto, 1 resident, 2 streaming
+  int waves;  // 0 auto
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+fca_status fail(fca_ctx* c, fca_status st, const std::string& msg) {
+  if (c) c->err = msg; else g_init_error = msg;
+  return st;
+}
+
+fca_status hip_fail(fca_ctx* c, hipError_t e, const char* where) {
+  return fail(c, FCA_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Arena {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t count) {
+    const size_t at = align_up(off, 256);
+    off = at + count * sizeof(T);
+    return at;
+  }
+};
+
+int auto_waves(const fca_ctx* c) {
+  if (c->waves > 0) return c->waves;
+  for (int w : {1, 2, 4})
+    if (c->ks->as_resident_fits(c->N, w)) return w;
+  return 4;
+}
+
+fca_status post_check(fca_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  if (!c->check_finite) return FCA_OK;
+  const DevState& s = c->s;
+  if ((e = hipMemsetAsync(s.flag, 0, sizeof(int), c->stream)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+  e = fca::launch_check_finite(s.vs, (long long)c->F * c->J * s.Npad, s.flag, c->stream);
+  if (e == hipSuccess && c->method == FCA_METHOD_AS) {
+    e = fca::launch_check_finite(s.lam, (long long)c->F * c->J * c->I, s.flag, c->stream);
+    if (e == hipSuccess)
+      e = fca::launch_check_finite(reinterpret_cast<const float*>(s.P), 2LL * c->F * c->I * c->I, s.flag, c->stream);
+  } else if (e == hipSuccess) {
+    e = fca::launch_check_finite(reinterpret_cast<const float*>(s.R), 2LL * c->F * c->J * c->I * c->I, s.flag, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "finiteness check");
+  int h = 0;
+  if ((e = hipMemcpyAsync(&h, s.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "hipMemcpyAsync");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  if (h) return fail(c, FCA_ERR_NONFINITE, "non-finite parameter values after the update");
+  return FCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J, const fca_c64* x,
+                    const float* v0, const float* lam0, const fca_c64* P0, const fca_c64* R0,
+                    void* hip_stream) {
+  if (!out) return fail(nullptr, FCA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (method != FCA_METHOD_AS && method != FCA_METHOD_EM) return fail(nullptr, FCA_ERR_ARG, "unknown method");
+  if (F < 1 || N < 1 || I < 1 || J < 1) return fail(nullptr, FCA_ERR_ARG, "F, N, I, J must be positive");
+  if (I > 8 || J > 9) return fail(nullptr, FCA_ERR_UNSUPPORTED, "supported sizes are 1 <= I <= 8, 1 <= J <= 9");
+  if (N < I) return fail(nullptr, FCA_ERR_ARG, "N must be at least I (the weighted covariances are singular otherwise)");
+  const long long Npad = ((long long)N + 63) / 64 * 64;
+  const int mx = I > J ? I : J;
+  if ((long long)F * Npad * 2 * mx >= (1LL << 31)) return fail(nullptr, FCA_ERR_ARG, "problem too large (N*F*max(I,J) >= 2^31)");
+  if (!x || !v0 || !lam0 || !P0) return fail(nullptr, FCA_ERR_ARG, "x, v0, lam0 and P0 must be non-NULL device pointers");
+  if (!aligned(x, 8) || !aligned(P0, 8) || !aligned(v0, 4) || !aligned(lam0, 4) || (R0 && !aligned(R0, 8)))
+    return fail(nullptr, FCA_ERR_ARG, "misaligned pointer (complex arrays need 8-byte, float arrays 4-byte alignment)");
+  if (method == FCA_METHOD_AS && R0) return fail(nullptr, FCA_ERR_ARG, "R0 must be NULL for FCA_METHOD_AS");
+  const KernelSet* ks = fca::kernel_set(I, J);
+  if (!ks) return fail(nullptr, FCA_ERR_UNSUPPORTED, "(I, J) not instantiated");
+
+  fca_ctx* c = new (std::nothrow) fca_ctx();
+  if (!c) return fail(nullptr, FCA_ERR_HIP, "host allocation failed");
+  c->method = method; c->F = F; c->N = N; c->I = I; c->J = J;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->arena = nullptr;
+
+  DevState& s = c->s;
+  s.F = F; s.N = N; s.Npad = (int)Npad; s.K = 1;
+  s.nchunk = (N + fca::kChunk - 1) / fca::kChunk;
+  s.nchunk_em = (N + fca::kChunkEm - 1) / fca::kChunkEm;
+  const size_t FJI = (size_t)F * J * I, FII = (size_t)F * I * I, FJII = (size_t)F * J * I * I;
+  Arena a;
+  const size_t o_xs = a.take<float>((size_t)F * 2 * I * Npad);
+  const size_t o_vs = a.take<float>((size_t)F * J * Npad);
+  const size_t o_lam = a.take<float>(FJI);
+  const size_t o_P = a.take<float2>(FII);
+  const size_t o_Bm = a.take<float2>(FII);
+  const bool em = method == FCA_METHOD_EM;
+  const size_t o_R = em ? a.take<float2>(FJII) : 0;
+  const size_t o_Ri = em ? a.take<float2>(FJII) : 0;
+  size_t nA = (size_t)F * s.nchunk * J * I;
+  if (em) nA = (size_t)F * s.nchunk_em * J * I * I;
+  const size_t o_pA = a.take<float>(nA);
+  const size_t o_pB = em ? 0 : a.take<float>((size_t)F * s.nchunk * I * I * I);
+  const size_t o_pL = a.take<double>((size_t)F * (s.nchunk > s.nchunk_em ? s.nchunk : s.nchunk_em));
+  const size_t o_llf = a.take<double>(F);
+  const size_t o_ll = a.take<double>(1);
+  const size_t o_flag = a.take<int>(1);
+  hipError_t e = hipMalloc(&c->arena, a.off);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "hipMalloc");
+  }
+  char* base = static_cast<char*>(c->arena);
+  s.xs = reinterpret_cast<float*>(base + o_xs);
+  s.vs = reinterpret_cast<float*>(base + o_vs);
+  s.lam = reinterpret_cast<float*>(base + o_lam);
+  s.P = reinterpret_cast<float2*>(base + o_P);
+  s.Bm = reinterpret_cast<float2*>(base + o_Bm);
+  s.R = em ? reinterpret_cast<float2*>(base + o_R) : nullptr;
+  s.Rinv = em ? reinterpret_cast<float2*>(base + o_Ri) : nullptr;
+  s.partA = reinterpret_cast<float*>(base + o_pA);
+  s.partB = em ? nullptr : reinterpret_cast<float*>(base + o_pB);
+  s.partL = reinterpret_cast<double*>(base + o_pL);
+  s.llf = reinterpret_cast<double*>(base + o_llf);
+  s.ll = reinterpret_cast<double*>(base + o_ll);
+  s.flag = reinterpret_cast<int*>(base + o_flag);
+
+  hipStream_t st = c->stream;
+  if ((e = fca::launch_pack_x(reinterpret_cast<const float2*>(x), const_cast<float*>(s.xs), F, N, I, s.Npad, st)) != hipSuccess ||
+      (e = fca::launch_pack_v(v0, s.vs, F, N, J, s.Npad, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.lam, lam0, FJI * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.P, P0, FII * sizeof(float2), hipMemcpyDeviceToDevice, st)) != hipSuccess) {
+    fca_status r = hip_fail(nullptr, e, "fca_init upload");
+    (void)hipFree(c->arena);
+    delete c;
+    return r;
+  }
+  if (em) {
+    if (R0) {
+      e = hipMemcpyAsync(s.R, R0, FJII * sizeof(float2), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = ks->em_rinv(s, st);
+    } else {
+      e = ks->em_from_as(s, st);
+    }
+    if (e != hipSuccess) {
+      fca_status r = hip_fail(nullptr, e, "fca_init covariance setup");
+      (void)hipFree(c->arena);
+      delete c;
+      return r;
+    }
+  }
+  *out = c;
+  return FCA_OK;
+}
+
+fca_status fastfca_as_iterate(fca_ctx* c, int n_iter) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (c->method != FCA_METHOD_AS) return fail(c, FCA_ERR_STATE, "fastfca_as_iterate on an FCA EM context");
+  if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
+  if (n_iter == 0) return FCA_OK;
+  const int waves = auto_waves(c);
+  const bool resident = c->path == 1 || (c->path == 0 && c->ks->as_resident_fits(c->N, waves));
+  if (resident) {
+    if (!c->ks->as_resident_fits(c->N, waves))
+      return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this N with this wave count");
+    for (int done = 0; done < n_iter;) {
+      const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
+      hipError_t e = c->ks->as_iter_resident(c->s, c->stream, step, waves);
+      if (e != hipSuccess) return hip_fail(c, e, "resident iteration");
+      done += step;
+    }
+  } else {
+    for (int it = 0; it < n_iter; ++it) {
+      hipError_t e = c->ks->as_iter_stream(c->s, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "streaming iteration");
+    }
+  }
+  return post_check(c);
+}
+
+fca_status fca_em_iterate(fca_ctx* c, int n_iter) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (c->method != FCA_METHOD_EM) return fail(c, FCA_ERR_STATE, "fca_em_iterate on a FastFCA-AS context");
+  if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
+  for (int it = 0; it < n_iter; ++it) {
+    hipError_t e = c->ks->em_iter(c->s, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "EM iteration");
+  }
+  return n_iter ? post_check(c) : FCA_OK;
+}
+
+fca_status fca_wiener_separate(fca_ctx* c, fca_c64* out) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!out || !aligned(out, 8)) return fail(c, FCA_ERR_ARG, "out must be an 8-byte aligned device pointer");
+  hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_wiener(c->s, c->stream, reinterpret_cast<float2*>(out))
+                                            : c->ks->em_wiener(c->s, c->stream, reinterpret_cast<float2*>(out));
+  if (e != hipSuccess) return hip_fail(c, e, "Wiener filter");
+  return FCA_OK;
+}
+
+fca_status fca_loglik(fca_ctx* c, double* out) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!out) return fail(c, FCA_ERR_ARG, "out is NULL");
+  hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_loglik(c->s, c->stream) : c->ks->em_loglik(c->s, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "log-likelihood");
+  double h = 0.0;
+  if ((e = hipMemcpyAsync(&h, c->s.ll, sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "hipMemcpyAsync");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  *out = h;
+  return FCA_OK;
+}
+
+fca_status fca_get_params(fca_ctx* c, float* v, float* lam, fca_c64* P_or_R) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if ((v && !aligned(v, 4)) || (lam && !aligned(lam, 4)) || (P_or_R && !aligned(P_or_R, 8)))
+    return fail(c, FCA_ERR_ARG, "misaligned pointer");
+  const DevState& s = c->s;
+  hipError_t e = hipSuccess;
+  if (v) e = fca::launch_unpack_v(s.vs, v, c->F, c->N, c->J, s.Npad, c->stream);
+  if (e == hipSuccess && lam && c->method == FCA_METHOD_AS)
+    e = hipMemcpyAsync(lam, s.lam, sizeof(float) * c->F * c->J * c->I, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && P_or_R) {
+    if (c->method == FCA_METHOD_AS)
+      e = hipMemcpyAsync(P_or_R, s.P, sizeof(float2) * c->F * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
+    else
+      e = hipMemcpyAsync(P_or_R, s.R, sizeof(float2) * c->F * c->J * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "fca_get_params");
+  return FCA_OK;
+}
+
+fca_status fca_set_params(fca_ctx* c, const float* v, const float* lam, const fca_c64* P_or_R) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if ((v && !aligned(v, 4)) || (lam && !aligned(lam, 4)) || (P_or_R && !aligned(P_or_R, 8)))
+    return fail(c, FCA_ERR_ARG, "misaligned pointer");
+  const DevState& s = c->s;
+  hipError_t e = hipSuccess;
+  if (v) e = fca::launch_pack_v(v, s.vs, c->F, c->N, c->J, s.Npad, c->stream);
+  if (e == hipSuccess && lam && c->method == FCA_METHOD_AS)
+    e = hipMemcpyAsync(s.lam, lam, sizeof(float) * c->F * c->J * c->I, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && P_or_R) {
+    if (c->method == FCA_METHOD_AS) {
+      e = hipMemcpyAsync(s.P, P_or_R, sizeof(float2) * c->F * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
+    } else {
+      e = hipMemcpyAsync(s.R, P_or_R, sizeof(float2) * c->F * c->J * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess) e = c->ks->em_rinv(s, c->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "fca_set_params");
+  return FCA_OK;
+}
+
+fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!key) return fail(c, FCA_ERR_ARG, "NULL key");
+  if (!std::strcmp(key, "K")) {
+    if (value < 1 || value > 64) return fail(c, FCA_ERR_ARG, "K must be in 1..64");
+    c->s.K = (int)value;
+  } else if (!std::strcmp(key, "check_finite")) {
+    if (value != 0 && value != 1) return fail(c, FCA_ERR_ARG, "check_finite must be 0 or 1");
+    c->check_finite = (int)value;
+  } else if (!std::strcmp(key, "path")) {
+    if (value < 0 || value > 2) return fail(c, FCA_ERR_ARG, "path must be 0, 1 or 2");
+    c->path = (int)value;
+  } else if (!std::strcmp(key, "waves")) {
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+      return fail(c, FCA_ERR_ARG, "waves must be 0 (auto), 1, 2 or 4");
+    c->waves = (int)value;
+  } else {
+    return fail(c, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
+  }
+  return FCA_OK;
+}
+
+const char* fca_last_error(const fca_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_init_error.c_str();
+}
+
+void fca_destroy(fca_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->arena) (void)hipFree(c->arena);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Layout conversion, finiteness check and the final log-likelihood sum.
+#include "fca_state.h"
+
+namespace fca {
+
+// x [F][N][I] interleaved complex -> xs [F][2I][Npad] split planes (zero pad).
+__global__ void k_pack_x(const float2* __restrict__ x, float* __restrict__ xs, int F, int N, int I, int Npad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)F * Npad) return;
+  const int f = (int)(t / Npad), n = (int)(t % Npad);
+  float* dst = xs + (size_t)f * 2 * I * Npad + n;
+  for (int i = 0; i < I; ++i) {
+    const float2 z = (n < N) ? x[((size_t)f * N + n) * I + i] : make_float2(0.f, 0.f);
+    dst[(size_t)i * Npad] = z.x;
+    dst[(size_t)(I + i) * Npad] = z.y;
+  }
+}
+
+// v [F][N][J] -> vs [F][J][Npad] (padding set to 1 so that unused lanes stay finite).
+__global__ void k_pack_v(const float* __restrict__ v, float* __restrict__ vs, int F, int N, int J, int Npad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)F * Npad) return;
+  const int f = (int)(t / Npad), n = (int)(t % Npad);
+  for (int j = 0; j < J; ++j)
+    vs[((size_t)f * J + j) * Npad + n] = (n < N) ? v[((size_t)f * N + n) * J + j] : 1.f;
+}
+
+__global__ void k_unpack_v(const float* __restrict__ vs, float* __restrict__ v, int F, int N, int J, int Npad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)F * N) return;
+  const int f = (int)(t / N), n = (int)(t % N);
+  for (int j = 0; j < J; ++j) v[((size_t)f * N + n) * J + j] = vs[((size_t)f * J + j) * Npad + n];
+}
+
+__global__ void k_check_finite(const float* __restrict__ a, long long n, int* flag) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (; t < n; t += stride) bad = bad || !isfinite(a[t]);
+  if (bad) atomicOr(flag, 1);
+}
+
+// Deterministic sum of the per-bin log-likelihoods (one workgroup).
+__global__ void k_sum_f(const double* __restrict__ llf, int F, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int f = threadIdx.x; f < F; f += blockDim.x) acc += llf[f];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int m = 128; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+static unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_pack_x(const float2* x, float* xs, int F, int N, int I, int Npad, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_x, dim3(blocks_for((long long)F * Npad, 256)), dim3(256), 0, st, x, xs, F, N, I, Npad);
+  return hipGetLastError();
+}
+hipError_t launch_pack_v(const float* v, float* vs, int F, int N, int J, int Npad, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_v, dim3(blocks_for((long long)F * Npad, 256)), dim3(256), 0, st, v, vs, F, N, J, Npad);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_v(const float* vs, float* v, int F, int N, int J, int Npad, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack_v, dim3(blocks_for((long long)F * N, 256)), dim3(256), 0, st, vs, v, F, N, J, Npad);
+  return hipGetLastError();
+}
+hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream_t st) {
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)b), dim3(256), 0, st, a, n, flag);
+  return hipGetLastError();
+}
+hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, st, llf, F, out);
+  return hipGetLastError();
+}
+
+}  // namespace fca

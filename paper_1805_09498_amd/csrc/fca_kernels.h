@@ -1,0 +1,890 @@
+// Templated kernels of libfastfca, instantiated per (I, J) by fca_inst_I*.hip.
+//
+// FastFCA-AS iteration (Section 4.4 of the paper), streaming form, three
+// launches per hybrid iteration:
+//   as_pass_a  per point: y = P^H x, d_i = sum_j v_j lambda_ji, diagonal
+//              posterior statistics (eq. 16-17), v update (eq. 19); per tile
+//              the partial sums of eq. 20.
+//   as_pass_b  lambda update (eq. 20) from the tile partials; per point the
+//              new d_i; per tile the partial weighted covariances of eq. 23.
+//   as_solve   per bin and column: P^-H column by LU, Cholesky solve of eq. 23.
+// The frequency-resident form (fca_resident.h) runs whole iterations inside
+// one workgroup per bin with the bin's data kept in registers.
+#pragma once
+
+#include "fca_device.h"
+#include "fca_state.h"
+
+namespace fca {
+
+// ----------------------------------------------------------------------------
+// Per-point arithmetic of FastFCA-AS.
+// ----------------------------------------------------------------------------
+
+// y = P^H x: y_i = sum_k conj(P_ki) x_k; returns |y_i|^2.
+template <int I>
+__device__ __forceinline__ void as_transform_pow(const float (&Pr)[I][I], const float (&Pi)[I][I],
+                                                 const float (&xr)[I], const float (&xi)[I],
+                                                 float (&y2)[I]) {
+#pragma unroll
+  for (int i = 0; i < I; ++i) {
+    float yr = 0.f, yi = 0.f;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      yr = fmaf(Pr[k][i], xr[k], yr);
+      yr = fmaf(Pi[k][i], xi[k], yr);
+      yi = fmaf(Pr[k][i], xi[k], yi);
+      yi = fmaf(-Pi[k][i], xr[k], yi);
+    }
+    y2[i] = fmaf(yr, yr, yi * yi);
+  }
+}
+
+template <int I>
+__device__ __forceinline__ void as_transform(const float (&Pr)[I][I], const float (&Pi)[I][I],
+                                             const float (&xr)[I], const float (&xi)[I],
+                                             float (&yr)[I], float (&yi)[I]) {
+#pragma unroll
+  for (int i = 0; i < I; ++i) {
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      a = fmaf(Pr[k][i], xr[k], a);
+      a = fmaf(Pi[k][i], xi[k], a);
+      b = fmaf(Pr[k][i], xi[k], b);
+      b = fmaf(-Pi[k][i], xr[k], b);
+    }
+    yr[i] = a; yi[i] = b;
+  }
+}
+
+// E-step statistics and v update of one point.
+//   r_ji = |mu~_ji|^2 + phi~_ji = g (g |y_i|^2 + e_ji),  g = v_j lambda_ji / d_i,
+//   e_ji = sum_{k != j} v_k lambda_ki  (eq. 16-17, phi~ = v lambda e / d),
+//   v_j <- (1/I) sum_i r_ji / lambda_ji                                (eq. 19)
+// and S_ji += r_ji / v_j(new) (the summand of eq. 20) when `take`.
+template <int I, int J>
+__device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&lam)[J][I],
+                                            const float (&ilamI)[J][I], float (&v)[J],
+                                            float (&S)[J][I], bool take) {
+  float r[J][I];
+#pragma unroll
+  for (int i = 0; i < I; ++i) {
+    float vl[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) vl[j] = v[j] * lam[j][i];
+    float pre[J];
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) { pre[j] = acc; acc += vl[j]; }
+    const float id = rcp(acc);
+    float suf = 0.f;
+#pragma unroll
+    for (int j = J - 1; j >= 0; --j) {
+      const float e = pre[j] + suf;
+      suf += vl[j];
+      const float g = vl[j] * id;
+      r[j][i] = g * fmaf(g, y2[i], e);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    float vn = 0.f;
+#pragma unroll
+    for (int i = 0; i < I; ++i) vn = fmaf(r[j][i], ilamI[j][i], vn);
+    v[j] = vn;
+    const float iv = take ? rcp(vn) : 0.f;
+#pragma unroll
+    for (int i = 0; i < I; ++i) S[j][i] = fmaf(r[j][i], iv, S[j][i]);
+  }
+}
+
+// 1 / d_i with d_i = sum_j v_j lambda_ji (the weights of eq. 23).
+template <int I, int J>
+__device__ __forceinline__ void as_point_weights(const float (&lam)[J][I], const float (&v)[J],
+                                                 float (&w)[I]) {
+#pragma unroll
+  for (int i = 0; i < I; ++i) {
+    float d = 0.f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
+    w[i] = rcp(d);
+  }
+}
+
+// Packed Hermitian slot layout of an I x I matrix in I*I reals: slot (a, b)
+// with a <= b holds Re A_ab, slot (b, a) with a < b holds Im A_ab.
+// Adds w * x x^H, i.e. A_ab += w x_a conj(x_b).
+template <int I>
+__device__ __forceinline__ void herm_rank1_acc(float (&A)[I * I], float w, const float (&xr)[I],
+                                               const float (&xi)[I]) {
+#pragma unroll
+  for (int a = 0; a < I; ++a) {
+    A[a * I + a] = fmaf(w, fmaf(xr[a], xr[a], xi[a] * xi[a]), A[a * I + a]);
+#pragma unroll
+    for (int b = a + 1; b < I; ++b) {
+      const float zr = fmaf(xr[a], xr[b], xi[a] * xi[b]);
+      const float zi = fmaf(xi[a], xr[b], -xr[a] * xi[b]);
+      A[a * I + b] = fmaf(w, zr, A[a * I + b]);
+      A[b * I + a] = fmaf(w, zi, A[b * I + a]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Block reduction of per-lane partial sums into a global vector.
+// ----------------------------------------------------------------------------
+template <int V>
+__device__ inline void block_sum_store(float (&a)[V], float* __restrict__ out, float* lds) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const float t = wave_sum(a[k]);
+    if (lane == 0) lds[wave * V + k] = t;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < V; k += blockDim.x) {
+    float t = 0.f;
+    for (int w = 0; w < nw; ++w) t += lds[w * V + k];
+    out[k] = t;
+  }
+  __syncthreads();
+}
+
+// Load the bin's P into registers from a staged copy.
+template <int I>
+__device__ __forceinline__ void load_P(const float2* __restrict__ Pg, float (&Pr)[I][I], float (&Pi)[I][I]) {
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      const float2 t = Pg[a * I + b];
+      Pr[a][b] = t.x; Pi[a][b] = t.y;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// FastFCA-AS streaming kernels.
+// ----------------------------------------------------------------------------
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ float2 sP[I * I];
+  __shared__ float sLam[J * I];
+  __shared__ float red[(kBlock / kWave) * J * I];
+  for (int t = threadIdx.x; t < I * I; t += kBlock) sP[t] = s.P[(size_t)f * I * I + t];
+  for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
+  __syncthreads();
+  float Pr[I][I], Pi[I][I], lam[J][I], ilamI[J][I];
+  load_P<I>(sP, Pr, Pi);
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      lam[j][i] = sLam[j * I + i];
+      ilamI[j][i] = 1.0f / (float(I) * lam[j][i]);
+    }
+  float S[J][I];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) S[j][i] = 0.f;
+
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  float* vf = s.vs + (size_t)f * J * s.Npad;
+#pragma unroll
+  for (int p = 0; p < kPts; ++p) {
+    const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+    if (n < s.N) {
+      float xr[I], xi[I], v[J];
+#pragma unroll
+      for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
+      float y2[I];
+      as_transform_pow<I>(Pr, Pi, xr, xi, y2);
+      as_point_em<I, J>(y2, lam, ilamI, v, S, true);
+#pragma unroll
+      for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[j];
+    }
+  }
+  float flat[J * I];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) flat[j * I + i] = S[j][i];
+  block_sum_store<J * I>(flat, s.partA + ((size_t)f * s.nchunk + chunk) * J * I, red);
+}
+
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ float sLam[J * I];
+  __shared__ float red[(kBlock / kWave) * I * I];
+  const float invN = 1.0f / float(s.N);
+  for (int t = threadIdx.x; t < J * I; t += kBlock) {
+    float acc = 0.f;
+    for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
+    sLam[t] = acc * invN;
+  }
+  __syncthreads();
+  float lam[J][I];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  const float* vf = s.vs + (size_t)f * J * s.Npad;
+  float xr[kPts][I], xi[kPts][I], w[kPts][I];
+#pragma unroll
+  for (int p = 0; p < kPts; ++p) {
+    const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+    const bool ok = n < s.N;
+    const int nn = ok ? n : 0;
+    float v[J];
+#pragma unroll
+    for (int i = 0; i < I; ++i) { xr[p][i] = xf[(size_t)i * s.Npad + nn]; xi[p][i] = xf[(size_t)(I + i) * s.Npad + nn]; }
+#pragma unroll
+    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
+    float wp[I];
+    as_point_weights<I, J>(lam, v, wp);
+#pragma unroll
+    for (int i = 0; i < I; ++i) w[p][i] = ok ? wp[i] : 0.f;
+  }
+  float* out = s.partB + ((size_t)f * s.nchunk + chunk) * I * I * I;
+#pragma unroll 1
+  for (int i = 0; i < I; ++i) {
+    float A[I * I];
+#pragma unroll
+    for (int k = 0; k < I * I; ++k) A[k] = 0.f;
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) herm_rank1_acc<I>(A, w[p][i], xr[p], xi[p]);
+    block_sum_store<I * I>(A, out + i * I * I, red);
+  }
+}
+
+// One lane per (bin, column); 8 bins per 64-lane workgroup.
+template <int I, int J>
+__global__ __launch_bounds__(64) void k_as_solve(DevState s) {
+  const int fl = threadIdx.x / 8, i = threadIdx.x % 8;
+  const int f = blockIdx.x * 8 + fl;
+  const bool act = (f < s.F) && (i < I);
+  __shared__ float sPr[8][I][I], sPi[8][I][I];
+  const float invN = 1.0f / float(s.N);
+  float Qr[I][I], Qi[I][I];
+  if (act) {
+    // lambda update (eq. 20): column i of every Lambda_j.
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float acc = 0.f;
+      for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + j * I + i];
+      s.lam[(size_t)f * J * I + j * I + i] = acc * invN;
+    }
+    // Q_i of eq. 23 from the tile partials.
+    float A[I * I];
+#pragma unroll
+    for (int k = 0; k < I * I; ++k) A[k] = 0.f;
+    for (int c = 0; c < s.nchunk; ++c) {
+      const float* src = s.partB + ((size_t)f * s.nchunk + c) * I * I * I + i * I * I;
+#pragma unroll
+      for (int k = 0; k < I * I; ++k) A[k] += src[k];
+    }
+#pragma unroll
+    for (int a = 0; a < I; ++a) {
+      Qr[a][a] = A[a * I + a] * invN; Qi[a][a] = 0.f;
+#pragma unroll
+      for (int b = a + 1; b < I; ++b) {
+        Qr[a][b] = A[a * I + b] * invN; Qi[a][b] = A[b * I + a] * invN;
+        Qr[b][a] = Qr[a][b]; Qi[b][a] = -Qi[a][b];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < I; ++a) {
+      const float2 t = s.P[(size_t)f * I * I + a * I + i];
+      sPr[fl][a][i] = t.x; sPi[fl][a][i] = t.y;
+    }
+  }
+  __syncthreads();
+  float Lr[I][I], Li[I][I], dinv[I];
+  if (act) cholesky<I>(Qr, Qi, Lr, Li, dinv);
+  for (int kk = 0; kk < s.K; ++kk) {
+    float pr[I], pi[I];
+    if (act) {
+      // b_i = column i of P^-H:  P^H b = e_i,  (P^H)_{rc} = conj(P_cr).
+      float Mr[I][I], Mi[I][I];
+#pragma unroll
+      for (int r = 0; r < I; ++r)
+#pragma unroll
+        for (int c = 0; c < I; ++c) { Mr[r][c] = sPr[fl][c][r]; Mi[r][c] = -sPi[fl][c][r]; }
+#pragma unroll
+      for (int r = 0; r < I; ++r) { pr[r] = (r == i) ? 1.f : 0.f; pi[r] = 0.f; }
+      lu_solve<I>(Mr, Mi, pr, pi);
+      cholesky_solve<I>(Lr, Li, dinv, pr, pi);  // p_i = Q_i^-1 b_i
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < I; ++a) { sPr[fl][a][i] = pr[a]; sPi[fl][a][i] = pi[a]; }
+    }
+    __syncthreads();
+  }
+  if (act) {
+#pragma unroll
+    for (int a = 0; a < I; ++a) s.P[(size_t)f * I * I + a * I + i] = make_float2(sPr[fl][a][i], sPi[fl][a][i]);
+  }
+}
+
+template <int I, int J>
+hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
+  dim3 grid(s.nchunk, s.F);
+  hipLaunchKernelGGL((k_as_pass_a<I, J>), grid, dim3(kBlock), 0, st, s);
+  hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(kBlock), 0, st, s);
+  hipLaunchKernelGGL((k_as_solve<I, J>), dim3((s.F + 7) / 8), dim3(64), 0, st, s);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Log-likelihood (eq. 14 for AS, eq. 5 for EM).
+// ----------------------------------------------------------------------------
+__device__ inline void block_sum_store_d(double a, double* out, double* lds) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const double t = wave_sum_d(a);
+  if (lane == 0) lds[wave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) u += lds[w];
+    *out = u;
+  }
+}
+
+// Per point: -sum_i ln d_i - sum_i |(P^H x)_i|^2 / d_i   (the n-dependent part of L2).
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_as_loglik(DevState s) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ float2 sP[I * I];
+  __shared__ float sLam[J * I];
+  __shared__ double red[kBlock / kWave];
+  for (int t = threadIdx.x; t < I * I; t += kBlock) sP[t] = s.P[(size_t)f * I * I + t];
+  for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
+  __syncthreads();
+  float Pr[I][I], Pi[I][I], lam[J][I];
+  load_P<I>(sP, Pr, Pi);
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  const float* vf = s.vs + (size_t)f * J * s.Npad;
+  double acc = 0.0;
+#pragma unroll
+  for (int p = 0; p < kPts; ++p) {
+    const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+    if (n < s.N) {
+      float xr[I], xi[I], v[J], y2[I];
+#pragma unroll
+      for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
+      as_transform_pow<I>(Pr, Pi, xr, xi, y2);
+      float t = 0.f;
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        float d = 0.f;
+#pragma unroll
+        for (int j = 0; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
+        t -= __logf(d) + y2[i] / d;
+      }
+      acc += (double)t;
+    }
+  }
+  block_sum_store_d(acc, s.partL + (size_t)f * s.nchunk + chunk, red);
+}
+
+// Per bin: sum of the tiles + N (2 ln|det P| - I ln pi).
+template <int I>
+__global__ void k_as_loglik_bin(DevState s) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= s.F) return;
+  float Mr[I][I], Mi[I][I];
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      const float2 t = s.P[(size_t)f * I * I + a * I + b];
+      Mr[a][b] = t.x; Mi[a][b] = t.y;
+    }
+  const double lad = (double)lu_logabsdet<I>(Mr, Mi);
+  double acc = 0.0;
+  for (int c = 0; c < s.nchunk; ++c) acc += s.partL[(size_t)f * s.nchunk + c];
+  s.llf[f] = acc + (double)s.N * (2.0 * lad - (double)I * 1.1447298858494002);
+}
+
+template <int I, int J>
+hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL((k_as_loglik<I, J>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s);
+  hipLaunchKernelGGL((k_as_loglik_bin<I>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
+  return launch_sum_f(s.llf, s.F, s.ll, st);
+}
+
+// ----------------------------------------------------------------------------
+// Wiener filter (eq. 3; AS form x_j = P^-H (g_j o y) from eq. 15-16).
+// ----------------------------------------------------------------------------
+// Bm[f] = P(f)^-H, one lane per (bin, column).
+template <int I>
+__global__ void k_p_inv_herm(DevState s) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = t / I, c = t % I;
+  if (f >= s.F) return;
+  float Mr[I][I], Mi[I][I], br[I], bi[I];
+#pragma unroll
+  for (int r = 0; r < I; ++r)
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      const float2 p = s.P[(size_t)f * I * I + k * I + r];
+      Mr[r][k] = p.x; Mi[r][k] = -p.y;
+    }
+#pragma unroll
+  for (int r = 0; r < I; ++r) { br[r] = (r == c) ? 1.f : 0.f; bi[r] = 0.f; }
+  lu_solve<I>(Mr, Mi, br, bi);
+#pragma unroll
+  for (int r = 0; r < I; ++r) s.Bm[(size_t)f * I * I + r * I + c] = make_float2(br[r], bi[r]);
+}
+
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __restrict__ out) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ float2 sP[I * I], sB[I * I];
+  __shared__ float sLam[J * I];
+  for (int t = threadIdx.x; t < I * I; t += kBlock) { sP[t] = s.P[(size_t)f * I * I + t]; sB[t] = s.Bm[(size_t)f * I * I + t]; }
+  for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
+  __syncthreads();
+  float Pr[I][I], Pi[I][I], Br[I][I], Bi[I][I], lam[J][I];
+  load_P<I>(sP, Pr, Pi);
+  load_P<I>(sB, Br, Bi);
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  const float* vf = s.vs + (size_t)f * J * s.Npad;
+#pragma unroll
+  for (int p = 0; p < kPts; ++p) {
+    const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+    if (n >= s.N) continue;
+    float xr[I], xi[I], v[J], yr[I], yi[I], id[I];
+#pragma unroll
+    for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+#pragma unroll
+    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
+    as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      float d = 0.f;
+#pragma unroll
+      for (int j = 0; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
+      id[i] = 1.0f / d;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float ur[I], ui[I];
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const float g = v[j] * lam[j][i] * id[i];
+        ur[i] = g * yr[i]; ui[i] = g * yi[i];
+      }
+      float2* o = out + (((size_t)j * s.F + f) * s.N + n) * I;
+#pragma unroll
+      for (int a = 0; a < I; ++a) {
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int i = 0; i < I; ++i) {
+          sr = fmaf(Br[a][i], ur[i], sr); sr = fmaf(-Bi[a][i], ui[i], sr);
+          si = fmaf(Br[a][i], ui[i], si); si = fmaf(Bi[a][i], ur[i], si);
+        }
+        o[a] = make_float2(sr, si);
+      }
+    }
+  }
+}
+
+template <int I, int J>
+hipError_t launch_as_wiener(const DevState& s, hipStream_t st, float2* out) {
+  hipLaunchKernelGGL((k_p_inv_herm<I>), dim3((s.F * I + 63) / 64), dim3(64), 0, st, s);
+  hipLaunchKernelGGL((k_as_wiener<I, J>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s, out);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Conventional FCA EM (Section 3.3).
+// ----------------------------------------------------------------------------
+template <int I, int J>
+struct EmShared {
+  float Rr[J][I][I], Ri[J][I][I];  // S_j
+  float Sr[J][I][I], Si[J][I][I];  // S_j^-1
+};
+
+template <int I, int J>
+__device__ inline void em_load_shared(const DevState& s, int f, EmShared<I, J>& sh) {
+  for (int t = threadIdx.x; t < J * I * I; t += blockDim.x) {
+    const int j = t / (I * I), a = (t / I) % I, b = t % I;
+    const float2 r = s.R[(size_t)f * J * I * I + t];
+    const float2 q = s.Rinv[(size_t)f * J * I * I + t];
+    sh.Rr[j][a][b] = r.x; sh.Ri[j][a][b] = r.y;
+    sh.Sr[j][a][b] = q.x; sh.Si[j][a][b] = q.y;
+  }
+}
+
+// C = sum_j v_j S_j (upper triangle).
+template <int I, int J>
+__device__ __forceinline__ void em_model_cov(const EmShared<I, J>& sh, const float (&v)[J],
+                                             float (&Cr)[I][I], float (&Ci)[I][I]) {
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = a; b < I; ++b) {
+      float cr = 0.f, ci = 0.f;
+#pragma unroll
+      for (int j = 0; j < J; ++j) { cr = fmaf(v[j], sh.Rr[j][a][b], cr); ci = fmaf(v[j], sh.Ri[j][a][b], ci); }
+      Cr[a][b] = cr; Ci[a][b] = ci;
+    }
+}
+
+// One EM point: E-step (eq. 7-8) for every j, v update (eq. 9), summand of
+// eq. 10 reduced over the wave into the wave's LDS accumulator.
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_em_pass(DevState s) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ EmShared<I, J> sh;
+  __shared__ float acc[kBlock / kWave][J][I * I];
+  em_load_shared<I, J>(s, f, sh);
+  for (int t = threadIdx.x; t < (kBlock / kWave) * J * I * I; t += kBlock) (&acc[0][0][0])[t] = 0.f;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int n = chunk * kChunkEm + threadIdx.x;
+  const bool ok = n < s.N;
+  const int nn = ok ? n : 0;
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  float* vf = s.vs + (size_t)f * J * s.Npad;
+  float xr[I], xi[I], v[J];
+#pragma unroll
+  for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
+#pragma unroll
+  for (int j = 0; j < J; ++j) v[j] = ok ? vf[(size_t)j * s.Npad + nn] : 1.f;
+  float Cr[I][I], Ci[I][I], Xr[I][I], Xi[I][I];
+  em_model_cov<I, J>(sh, v, Cr, Ci);
+  herm_inverse<I>(Cr, Ci, Xr, Xi);  // C^-1 (one inversion per point)
+#pragma unroll 1
+  for (int j = 0; j < J; ++j) {
+    // K = S_j C^-1 (first product); W_j = v_j K.
+    float Kr[I][I], Ki[I][I];
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) {
+        float kr = 0.f, ki = 0.f;
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+          kr = fmaf(sh.Rr[j][a][c], Xr[c][b], kr); kr = fmaf(-sh.Ri[j][a][c], Xi[c][b], kr);
+          ki = fmaf(sh.Rr[j][a][c], Xi[c][b], ki); ki = fmaf(sh.Ri[j][a][c], Xr[c][b], ki);
+        }
+        Kr[a][b] = kr; Ki[a][b] = ki;
+      }
+    const float vj = v[j];
+    // mu_j = v_j K x  (eq. 7)
+    float mr[I], mi[I];
+#pragma unroll
+    for (int a = 0; a < I; ++a) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int c = 0; c < I; ++c) {
+        sr = fmaf(Kr[a][c], xr[c], sr); sr = fmaf(-Ki[a][c], xi[c], sr);
+        si = fmaf(Kr[a][c], xi[c], si); si = fmaf(Ki[a][c], xr[c], si);
+      }
+      mr[a] = vj * sr; mi[a] = vj * si;
+    }
+    // Rhat = mu mu^H + v_j S_j - v_j^2 K S_j  (eq. 8, second product), upper triangle.
+    float Hr[I][I], Hi[I][I];
+    const float vj2 = vj * vj;
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = a; b < I; ++b) {
+        float kr = 0.f, ki = 0.f;
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+          kr = fmaf(Kr[a][c], sh.Rr[j][c][b], kr); kr = fmaf(-Ki[a][c], sh.Ri[j][c][b], kr);
+          ki = fmaf(Kr[a][c], sh.Ri[j][c][b], ki); ki = fmaf(Ki[a][c], sh.Rr[j][c][b], ki);
+        }
+        const float mmr = fmaf(mr[a], mr[b], mi[a] * mi[b]);
+        const float mmi = fmaf(mi[a], mr[b], -mr[a] * mi[b]);
+        Hr[a][b] = mmr + fmaf(vj, sh.Rr[j][a][b], -vj2 * kr);
+        Hi[a][b] = (a == b) ? 0.f : mmi + fmaf(vj, sh.Ri[j][a][b], -vj2 * ki);
+      }
+    // v_j <- Re tr(S_j^-1 Rhat) / I  (eq. 9, with the current S_j)
+    float tr = 0.f;
+#pragma unroll
+    for (int a = 0; a < I; ++a) {
+      tr = fmaf(sh.Sr[j][a][a], Hr[a][a], tr);
+#pragma unroll
+      for (int b = a + 1; b < I; ++b)
+        tr = fmaf(2.f, fmaf(sh.Sr[j][a][b], Hr[a][b], sh.Si[j][a][b] * Hi[a][b]), tr);
+    }
+    const float vn = tr / float(I);
+    if (ok) vf[(size_t)j * s.Npad + n] = vn;
+    const float iv = ok ? 1.0f / vn : 0.f;
+    // summand of eq. 10 (with the new v_j), packed Hermitian slots
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = a; b < I; ++b) {
+        const float t1 = wave_sum(Hr[a][b] * iv);
+        if (lane == 0) acc[wave][j][a * I + b] += t1;
+        if (b > a) {
+          const float t2 = wave_sum(Hi[a][b] * iv);
+          if (lane == 0) acc[wave][j][b * I + a] += t2;
+        }
+      }
+  }
+  __syncthreads();
+  float* out = s.partA + ((size_t)f * s.nchunk_em + chunk) * J * I * I;
+  for (int t = threadIdx.x; t < J * I * I; t += kBlock) {
+    float u = 0.f;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) u += (&acc[w][0][0])[t];
+    out[t] = u;
+  }
+}
+
+// S_j <- (1/N) sum over tiles (eq. 10), exactly Hermitian; S_j^-1 for the next
+// v update.  One lane per (bin, source).
+template <int I, int J>
+__global__ void k_em_finalize(DevState s) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = t / J, j = t % J;
+  if (f >= s.F) return;
+  float A[I * I];
+#pragma unroll
+  for (int k = 0; k < I * I; ++k) A[k] = 0.f;
+  for (int c = 0; c < s.nchunk_em; ++c) {
+    const float* src = s.partA + ((size_t)f * s.nchunk_em + c) * J * I * I + j * I * I;
+#pragma unroll
+    for (int k = 0; k < I * I; ++k) A[k] += src[k];
+  }
+  const float invN = 1.0f / float(s.N);
+  float Rr[I][I], Ri[I][I], Xr[I][I], Xi[I][I];
+#pragma unroll
+  for (int a = 0; a < I; ++a) {
+    Rr[a][a] = A[a * I + a] * invN; Ri[a][a] = 0.f;
+#pragma unroll
+    for (int b = a + 1; b < I; ++b) {
+      Rr[a][b] = A[a * I + b] * invN; Ri[a][b] = A[b * I + a] * invN;
+      Rr[b][a] = Rr[a][b]; Ri[b][a] = -Ri[a][b];
+    }
+  }
+  herm_inverse<I>(Rr, Ri, Xr, Xi);
+  float2* R = s.R + ((size_t)f * J + j) * I * I;
+  float2* X = s.Rinv + ((size_t)f * J + j) * I * I;
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      R[a * I + b] = make_float2(Rr[a][b], Ri[a][b]);
+      X[a * I + b] = make_float2(Xr[a][b], Xi[a][b]);
+    }
+}
+
+template <int I, int J>
+hipError_t launch_em_iter(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL((k_em_pass<I, J>), dim3(s.nchunk_em, s.F), dim3(kBlock), 0, st, s);
+  hipLaunchKernelGGL((k_em_finalize<I, J>), dim3((s.F * J + 63) / 64), dim3(64), 0, st, s);
+  return hipGetLastError();
+}
+
+// S_j = P^-H diag(lambda_j) P^-1 (eq. 12) and S_j^-1 = P diag(1/lambda_j) P^H,
+// one lane per (bin, source): the EM starting point equal to an AS state.
+template <int I, int J>
+__global__ void k_em_from_as(DevState s) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = t / J, j = t % J;
+  if (f >= s.F) return;
+  float Pr[I][I], Pi[I][I], Ur[I][I], Ui[I][I];  // U = P^-1
+  load_P<I>(s.P + (size_t)f * I * I, Pr, Pi);
+#pragma unroll
+  for (int c = 0; c < I; ++c) {
+    float Mr[I][I], Mi[I][I], br[I], bi[I];
+#pragma unroll
+    for (int a = 0; a < I; ++a) {
+#pragma unroll
+      for (int b = 0; b < I; ++b) { Mr[a][b] = Pr[a][b]; Mi[a][b] = Pi[a][b]; }
+      br[a] = (a == c) ? 1.f : 0.f; bi[a] = 0.f;
+    }
+    lu_solve<I>(Mr, Mi, br, bi);
+#pragma unroll
+    for (int a = 0; a < I; ++a) { Ur[a][c] = br[a]; Ui[a][c] = bi[a]; }
+  }
+  float lam[I];
+#pragma unroll
+  for (int i = 0; i < I; ++i) lam[i] = s.lam[((size_t)f * J + j) * I + i];
+  float2* R = s.R + ((size_t)f * J + j) * I * I;
+  float2* X = s.Rinv + ((size_t)f * J + j) * I * I;
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      // (U^H diag(lam) U)_ab = sum_k conj(U_ka) lam_k U_kb
+      float rr = 0.f, ri = 0.f, xr = 0.f, xi = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        const float ar = Ur[k][a] * lam[k], ai = -Ui[k][a] * lam[k];
+        rr += ar * Ur[k][b] - ai * Ui[k][b];
+        ri += ar * Ui[k][b] + ai * Ur[k][b];
+        // (P diag(1/lam) P^H)_ab = sum_k P_ak / lam_k conj(P_bk)
+        const float pr = Pr[a][k] / lam[k], pi = Pi[a][k] / lam[k];
+        xr += pr * Pr[b][k] + pi * Pi[b][k];
+        xi += pi * Pr[b][k] - pr * Pi[b][k];
+      }
+      R[a * I + b] = make_float2(rr, ri);
+      X[a * I + b] = make_float2(xr, xi);
+    }
+}
+
+template <int I, int J>
+hipError_t launch_em_from_as(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL((k_em_from_as<I, J>), dim3((s.F * J + 63) / 64), dim3(64), 0, st, s);
+  return hipGetLastError();
+}
+
+// S_j^-1 of caller-given S_j (its upper triangle; the stored S_j is made
+// exactly Hermitian from it).
+template <int I, int J>
+__global__ void k_em_rinv(DevState s) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = t / J, j = t % J;
+  if (f >= s.F) return;
+  float2* R = s.R + ((size_t)f * J + j) * I * I;
+  float Rr[I][I], Ri[I][I], Xr[I][I], Xi[I][I];
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = a; b < I; ++b) {
+      const float2 r = R[a * I + b];
+      Rr[a][b] = r.x; Ri[a][b] = (a == b) ? 0.f : r.y;
+      Rr[b][a] = r.x; Ri[b][a] = -Ri[a][b];
+    }
+  herm_inverse<I>(Rr, Ri, Xr, Xi);
+  float2* X = s.Rinv + ((size_t)f * J + j) * I * I;
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      R[a * I + b] = make_float2(Rr[a][b], Ri[a][b]);
+      X[a * I + b] = make_float2(Xr[a][b], Xi[a][b]);
+    }
+}
+
+template <int I, int J>
+hipError_t launch_em_rinv(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL((k_em_rinv<I, J>), dim3((s.F * J + 63) / 64), dim3(64), 0, st, s);
+  return hipGetLastError();
+}
+
+// L1 per point: -ln det C - x^H C^-1 x (Cholesky of C).
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_em_loglik(DevState s) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ EmShared<I, J> sh;
+  __shared__ double red[kBlock / kWave];
+  em_load_shared<I, J>(s, f, sh);
+  __syncthreads();
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  const float* vf = s.vs + (size_t)f * J * s.Npad;
+  const int n = chunk * kChunkEm + threadIdx.x;
+  double acc = 0.0;
+  if (n < s.N) {
+    float xr[I], xi[I], v[J];
+#pragma unroll
+    for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+#pragma unroll
+    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
+    float Cr[I][I], Ci[I][I], Lr[I][I], Li[I][I], dinv[I];
+    em_model_cov<I, J>(sh, v, Cr, Ci);
+    cholesky<I>(Cr, Ci, Lr, Li, dinv);
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      float sr = xr[k], si = xi[k];
+#pragma unroll
+      for (int m = 0; m < k; ++m) {
+        sr -= Lr[k][m] * xr[m] - Li[k][m] * xi[m];
+        si -= Lr[k][m] * xi[m] + Li[k][m] * xr[m];
+      }
+      xr[k] = sr * dinv[k]; xi[k] = si * dinv[k];
+      t -= 2.f * __logf(Lr[k][k]) + xr[k] * xr[k] + xi[k] * xi[k];
+    }
+    acc = (double)t;
+  }
+  block_sum_store_d(acc, s.partL + (size_t)f * s.nchunk_em + chunk, red);
+}
+
+template <int I>
+__global__ void k_em_loglik_bin(DevState s) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= s.F) return;
+  double acc = 0.0;
+  for (int c = 0; c < s.nchunk_em; ++c) acc += s.partL[(size_t)f * s.nchunk_em + c];
+  s.llf[f] = acc - (double)s.N * (double)I * 1.1447298858494002;
+}
+
+template <int I, int J>
+hipError_t launch_em_loglik(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL((k_em_loglik<I, J>), dim3(s.nchunk_em, s.F), dim3(kBlock), 0, st, s);
+  hipLaunchKernelGGL((k_em_loglik_bin<I>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
+  return launch_sum_f(s.llf, s.F, s.ll, st);
+}
+
+// x_j = v_j S_j C^-1 x (eq. 3).
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_em_wiener(DevState s, float2* __restrict__ out) {
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ EmShared<I, J> sh;
+  em_load_shared<I, J>(s, f, sh);
+  __syncthreads();
+  const int n = chunk * kChunkEm + threadIdx.x;
+  if (n >= s.N) return;
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  const float* vf = s.vs + (size_t)f * J * s.Npad;
+  float xr[I], xi[I], v[J];
+#pragma unroll
+  for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+#pragma unroll
+  for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
+  float Cr[I][I], Ci[I][I], Lr[I][I], Li[I][I], dinv[I];
+  em_model_cov<I, J>(sh, v, Cr, Ci);
+  cholesky<I>(Cr, Ci, Lr, Li, dinv);
+  cholesky_solve<I>(Lr, Li, dinv, xr, xi);  // z = C^-1 x
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    float2* o = out + (((size_t)j * s.F + f) * s.N + n) * I;
+#pragma unroll
+    for (int a = 0; a < I; ++a) {
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int c = 0; c < I; ++c) {
+        sr = fmaf(sh.Rr[j][a][c], xr[c], sr); sr = fmaf(-sh.Ri[j][a][c], xi[c], sr);
+        si = fmaf(sh.Rr[j][a][c], xi[c], si); si = fmaf(sh.Ri[j][a][c], xr[c], si);
+      }
+      o[a] = make_float2(v[j] * sr, v[j] * si);
+    }
+  }
+}
+
+template <int I, int J>
+hipError_t launch_em_wiener(const DevState& s, hipStream_t st, float2* out) {
+  hipLaunchKernelGGL((k_em_wiener<I, J>), dim3(s.nchunk_em, s.F), dim3(kBlock), 0, st, s, out);
+  return hipGetLastError();
+}
+
+}  // namespace fca

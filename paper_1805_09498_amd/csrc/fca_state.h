@@ -1,0 +1,64 @@
+// Device state shared by the kernels and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fca {
+
+// Streaming kernels: 256 lanes per workgroup, each lane owns kPts points of a
+// tile; one tile covers kChunk consecutive frames of one frequency bin.
+constexpr int kBlock = 256;
+constexpr int kPts = 4;
+constexpr int kChunk = kBlock * kPts;
+constexpr int kChunkEm = kBlock;  // FCA EM: one point per lane
+
+// Internal layouts (library-owned):
+//   xs   [F][2I][Npad]  split-complex mixture: plane i = Re x_i, plane I+i = Im x_i
+//   vs   [F][J][Npad]   v_j(n,f), frames contiguous
+//   lam  [F][J][I]      ABI layout
+//   P    [F][I][I]      ABI layout (interleaved complex)
+//   R    [F][J][I][I]   ABI layout; Rinv the same for S_j^-1 (EM only)
+struct DevState {
+  int F, N, Npad;
+  int nchunk;     // tiles per bin of the AS streaming kernels
+  int nchunk_em;  // tiles per bin of the EM kernels
+  int K;          // fixed-point steps per hybrid iteration
+  const float* xs;
+  float* vs;
+  float* lam;
+  float2* P;
+  float2* R;
+  float2* Rinv;
+  float2* Bm;     // scratch [F][I][I]
+  float* partA;   // scratch per-tile partial sums
+  float* partB;
+  double* partL;  // [F][max(nchunk, nchunk_em)]
+  double* llf;    // [F]
+  double* ll;     // [1]
+  int* flag;      // [1]
+};
+
+// Host launchers of one (I, J) instantiation.
+struct KernelSet {
+  hipError_t (*as_iter_stream)(const DevState&, hipStream_t);
+  hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
+  int (*as_resident_fits)(int N, int waves);
+  hipError_t (*em_iter)(const DevState&, hipStream_t);
+  hipError_t (*as_loglik)(const DevState&, hipStream_t);
+  hipError_t (*em_loglik)(const DevState&, hipStream_t);
+  hipError_t (*as_wiener)(const DevState&, hipStream_t, float2* out);
+  hipError_t (*em_wiener)(const DevState&, hipStream_t, float2* out);
+  hipError_t (*em_from_as)(const DevState&, hipStream_t);
+  hipError_t (*em_rinv)(const DevState&, hipStream_t);
+};
+
+// Non-templated kernels' launchers (fca_common.hip).
+hipError_t launch_pack_x(const float2* x, float* xs, int F, int N, int I, int Npad, hipStream_t st);
+hipError_t launch_pack_v(const float* v, float* vs, int F, int N, int J, int Npad, hipStream_t st);
+hipError_t launch_unpack_v(const float* vs, float* v, int F, int N, int J, int Npad, hipStream_t st);
+hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream_t st);
+hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st);
+
+const KernelSet* kernel_set(int I, int J);  // NULL if not instantiated
+
+}  // namespace fca

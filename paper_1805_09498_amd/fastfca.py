@@ -1,0 +1,197 @@
+"""Python binding of libfastfca (ctypes).  Argument marshalling only: every
+step of FCA / FastFCA-AS runs in the library's HIP kernels.
+
+The functions carry the names of the C ABI (include/fastfca.h):
+``fca_init``, ``fastfca_as_iterate``, ``fca_em_iterate``,
+``fca_wiener_separate``, ``fca_loglik``, ``fca_get_params``,
+``fca_set_params``, ``fca_set_option``, ``fca_last_error``, ``fca_destroy``.
+Arrays are torch tensors on the GPU in the ABI layouts (complex64 /
+float32, C-contiguous); PyTorch provides the device memory and the stream.
+
+If the shared library has not been built, importing this module raises
+ImportError: there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastfca.so")
+
+FCA_OK = 0
+FCA_ERR_ARG = -1
+FCA_ERR_UNSUPPORTED = -2
+FCA_ERR_HIP = -3
+FCA_ERR_STATE = -4
+FCA_ERR_NONFINITE = -5
+
+FCA_METHOD_AS = 0
+FCA_METHOD_EM = 1
+
+EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
+            "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
+            "fca_last_error", "fca_destroy")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, c = ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p
+    lib.fca_init.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, vp, vp, vp, vp, vp, vp]
+    lib.fca_init.restype = i
+    lib.fastfca_as_iterate.argtypes = [vp, i]
+    lib.fastfca_as_iterate.restype = i
+    lib.fca_em_iterate.argtypes = [vp, i]
+    lib.fca_em_iterate.restype = i
+    lib.fca_wiener_separate.argtypes = [vp, vp]
+    lib.fca_wiener_separate.restype = i
+    lib.fca_loglik.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.fca_loglik.restype = i
+    lib.fca_get_params.argtypes = [vp, vp, vp, vp]
+    lib.fca_get_params.restype = i
+    lib.fca_set_params.argtypes = [vp, vp, vp, vp]
+    lib.fca_set_params.restype = i
+    lib.fca_set_option.argtypes = [vp, c, ctypes.c_longlong]
+    lib.fca_set_option.restype = i
+    lib.fca_last_error.argtypes = [vp]
+    lib.fca_last_error.restype = c
+    lib.fca_destroy.argtypes = [vp]
+    lib.fca_destroy.restype = None
+    return lib
+
+
+lib = _load()
+
+
+class FcaError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libfastfca status {status}: {message}")
+        self.status = status
+
+
+def fca_last_error(ctx=None):
+    return lib.fca_last_error(ctx.handle if ctx is not None else None).decode()
+
+
+def _check(status, ctx=None):
+    if status != FCA_OK:
+        raise FcaError(status, fca_last_error(ctx))
+
+
+def _ptr(t, dtype, shape, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream), s
+
+
+class FcaContext:
+    """An opaque libfastfca context (one mixture, one method)."""
+
+    def __init__(self, handle, method, F, N, I, J, stream, keep):
+        self.handle = handle
+        self.method = method
+        self.F, self.N, self.I, self.J = F, N, I, J
+        self.stream = stream
+        self._keep = keep   # inputs stay referenced until the stream has consumed them
+
+    def __del__(self):
+        try:
+            fca_destroy(self)
+        except Exception:
+            pass
+
+
+def fca_init(method, x, v0, lam0, P0, R0=None, stream=None):
+    """fca_init: x [F][N][I] complex64, v0 [F][N][J] float32, lam0 [F][J][I]
+    float32, P0 [F][I][I] complex64, R0 [F][J][I][I] complex64 or None."""
+    if x.dim() != 3 or v0.dim() != 3:
+        raise ValueError("x must be [F][N][I] and v0 [F][N][J]")
+    F, N, I = x.shape
+    J = v0.shape[2]
+    args = [
+        _ptr(x, torch.complex64, (F, N, I), "x"),
+        _ptr(v0, torch.float32, (F, N, J), "v0"),
+        _ptr(lam0, torch.float32, (F, J, I), "lam0"),
+        _ptr(P0, torch.complex64, (F, I, I), "P0"),
+        _ptr(R0, torch.complex64, (F, J, I, I), "R0"),
+    ]
+    sh, s = _stream_handle(stream)
+    h = ctypes.c_void_p()
+    _check(lib.fca_init(ctypes.byref(h), int(method), F, N, I, J, *args, sh))
+    return FcaContext(h, int(method), F, N, I, J, s, (x, v0, lam0, P0, R0))
+
+
+def fastfca_as_iterate(ctx, n_iter):
+    _check(lib.fastfca_as_iterate(ctx.handle, int(n_iter)), ctx)
+
+
+def fca_em_iterate(ctx, n_iter):
+    _check(lib.fca_em_iterate(ctx.handle, int(n_iter)), ctx)
+
+
+def fca_wiener_separate(ctx, out=None):
+    """Returns (or fills) out [J][F][N][I] complex64."""
+    if out is None:
+        with torch.cuda.stream(ctx.stream):
+            out = torch.empty((ctx.J, ctx.F, ctx.N, ctx.I), dtype=torch.complex64, device="cuda")
+    p = _ptr(out, torch.complex64, (ctx.J, ctx.F, ctx.N, ctx.I), "out")
+    _check(lib.fca_wiener_separate(ctx.handle, p), ctx)
+    return out
+
+
+def fca_loglik(ctx):
+    out = ctypes.c_double()
+    _check(lib.fca_loglik(ctx.handle, ctypes.byref(out)), ctx)
+    return out.value
+
+
+def fca_get_params(ctx):
+    """AS: (v [F][N][J], lam [F][J][I], P [F][I][I]); EM: (v, None, R [F][J][I][I])."""
+    F, N, I, J = ctx.F, ctx.N, ctx.I, ctx.J
+    with torch.cuda.stream(ctx.stream):
+        v = torch.empty((F, N, J), dtype=torch.float32, device="cuda")
+        if ctx.method == FCA_METHOD_AS:
+            lam = torch.empty((F, J, I), dtype=torch.float32, device="cuda")
+            M = torch.empty((F, I, I), dtype=torch.complex64, device="cuda")
+        else:
+            lam = None
+            M = torch.empty((F, J, I, I), dtype=torch.complex64, device="cuda")
+    _check(lib.fca_get_params(ctx.handle, ctypes.c_void_p(v.data_ptr()),
+                              None if lam is None else ctypes.c_void_p(lam.data_ptr()),
+                              ctypes.c_void_p(M.data_ptr())), ctx)
+    return v, lam, M
+
+
+def fca_set_params(ctx, v=None, lam=None, P_or_R=None):
+    F, N, I, J = ctx.F, ctx.N, ctx.I, ctx.J
+    mshape = (F, I, I) if ctx.method == FCA_METHOD_AS else (F, J, I, I)
+    _check(lib.fca_set_params(ctx.handle, _ptr(v, torch.float32, (F, N, J), "v"),
+                              _ptr(lam, torch.float32, (F, J, I), "lam"),
+                              _ptr(P_or_R, torch.complex64, mshape, "P_or_R")), ctx)
+    ctx._keep = ctx._keep + (v, lam, P_or_R)
+
+
+def fca_set_option(ctx, key, value):
+    _check(lib.fca_set_option(ctx.handle, key.encode(), int(value)), ctx)
+
+
+def fca_destroy(ctx):
+    if ctx.handle is not None and ctx.handle.value:
+        lib.fca_destroy(ctx.handle)
+    ctx.handle = ctypes.c_void_p()

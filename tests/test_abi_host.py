@@ -1,0 +1,95 @@
+"""CPU-side checks of the C ABI: the built library loads, exports every
+function that include/fastfca.h declares, and rejects bad arguments on the
+host before touching any device (no GPU is needed for these calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastfca.h")
+LIB = os.path.join(ROOT, "paper_1805_09498_amd", "libfastfca.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libfastfca.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(f[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    L = ctypes.CDLL(LIB)
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    L.fca_init.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, vp, vp, vp, vp, vp, vp]
+    L.fca_init.restype = i
+    L.fca_last_error.argtypes = [vp]
+    L.fca_last_error.restype = ctypes.c_char_p
+    L.fca_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_longlong]
+    L.fca_set_option.restype = i
+    for name in ("fastfca_as_iterate", "fca_em_iterate"):
+        getattr(L, name).argtypes = [vp, i]
+        getattr(L, name).restype = i
+    L.fca_loglik.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.fca_loglik.restype = i
+    L.fca_destroy.argtypes = [vp]
+    L.fca_destroy.restype = None
+    return L
+
+
+def test_header_declares_the_expected_calls():
+    assert declared_functions() == sorted([
+        "fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
+        "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
+        "fca_last_error", "fca_destroy"])
+
+
+def test_every_declared_function_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation first
+
+
+def _init(lib, method=0, F=4, N=8, I=3, J=3, x=FAKE, v=FAKE, lam=FAKE, P=FAKE, R=None):
+    h = ctypes.c_void_p(123)
+    st = lib.fca_init(ctypes.byref(h), method, F, N, I, J, x, v, lam, P, R, None)
+    return st, h.value
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(I=9), -2), (dict(J=10), -2), (dict(I=0), -1), (dict(F=0), -1),
+    (dict(N=2, I=3), -1), (dict(x=None), -1), (dict(P=None), -1),
+    (dict(x=FAKE + 4), -1), (dict(v=FAKE + 2), -1), (dict(method=7), -1),
+    (dict(R=FAKE), -1),                      # AS contexts take no R0
+    (dict(F=1 << 20, N=1 << 12), -1),        # size limit
+])
+def test_init_rejects_bad_arguments_on_the_host(lib, kw, code):
+    st, h = _init(lib, **kw)
+    assert st == code
+    assert h is None
+    assert len(lib.fca_last_error(None)) > 0
+
+
+def test_null_context_calls(lib):
+    assert lib.fastfca_as_iterate(None, 1) == -1
+    assert lib.fca_em_iterate(None, 1) == -1
+    assert lib.fca_set_option(None, b"K", 1) == -1
+    d = ctypes.c_double()
+    assert lib.fca_loglik(None, ctypes.byref(d)) == -1
+    lib.fca_destroy(None)
+    assert lib.fca_init(None, 0, 1, 1, 1, 1, FAKE, FAKE, FAKE, FAKE, None, None) == -1
+
+
+def test_binding_has_no_fallback():
+    """The Python binding loads the HIP library or fails: there is no CPU
+    path and no import of the oracle."""
+    src = open(os.path.join(ROOT, "paper_1805_09498_amd", "fastfca.py")).read()
+    assert "oracle" not in src and "numpy" not in src
+    import paper_1805_09498_amd.fastfca as ff
+    assert ff.lib._name == ff.LIB_PATH

@@ -1,0 +1,92 @@
+"""GPU parity on edge and degenerate cases: every (I, J) corner of the
+instantiated range, ragged N (not a multiple of a wave or a tile), the
+minimum N = I, a single bin, a single source, a single microphone, more
+sources than microphones, and errors raised through the ABI."""
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_common import TOL_LOGLIK, TOL_PARAM, oracle_as, oracle_em, params, problem, rel, run_as, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ff():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1805_09498_amd import fastfca
+    return fastfca
+
+
+CASES = [
+    (1, 1, 3, 5), (1, 2, 4, 7), (2, 1, 5, 33), (2, 2, 3, 64), (2, 3, 7, 65),
+    (3, 1, 4, 100), (3, 3, 1, 3), (3, 5, 9, 1025), (4, 4, 6, 257), (5, 2, 5, 130),
+    (6, 4, 4, 300), (6, 7, 3, 2049), (7, 3, 3, 150), (8, 1, 2, 40), (8, 6, 3, 1100),
+    (8, 9, 2, 700), (4, 9, 5, 8),
+]
+
+
+@pytest.mark.parametrize("I,J,F,N", CASES)
+def test_as_edge_shapes(ff, I, J, F, N):
+    p = problem(I, J, F, N, seed=100 * I + 10 * J + F)
+    v_ref, lam_ref, P_ref = oracle_as(p, 1)
+    for path in (0, 2):
+        ctx = run_as(ff, p, 1, path=path)
+        v, lam, P = params(ff, ctx)
+        assert rel(v, v_ref) <= TOL_PARAM, (path, rel(v, v_ref))
+        assert rel(lam, lam_ref) <= TOL_PARAM, (path, rel(lam, lam_ref))
+        assert rel(P, P_ref) <= TOL_PARAM, (path, rel(P, P_ref))
+
+
+@pytest.mark.parametrize("I,J,F,N", CASES)
+def test_em_edge_shapes(ff, I, J, F, N):
+    p = problem(I, J, F, N, seed=100 * I + 10 * J + F)
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"])
+    ff.fca_em_iterate(ctx, 1)
+    v, _, R = params(ff, ctx)
+    v_ref, R_ref = oracle_em(p, oracle.as_spatial_cov(p.P0, p.lam0), 1)
+    assert rel(v, v_ref) <= TOL_PARAM
+    assert rel(R, R_ref) <= TOL_PARAM
+
+
+@pytest.mark.parametrize("I,J,F,N", [(1, 2, 4, 7), (2, 3, 7, 65), (8, 9, 2, 700), (6, 7, 3, 2049)])
+def test_loglik_and_wiener_edge(ff, I, J, F, N):
+    p = problem(I, J, F, N, seed=7 * I + J)
+    ctx = run_as(ff, p, 2)
+    v, lam, P = params(ff, ctx)
+    L = ff.fca_loglik(ctx)
+    assert abs(L - oracle.loglik_as(p.x, v, lam, P)) <= TOL_LOGLIK * abs(L)
+    s = ff.fca_wiener_separate(ctx).cpu().numpy().astype(np.complex128)
+    assert rel(s.sum(axis=0), p.x) <= 1e-5
+    assert rel(s, oracle.wiener_as(p.x, v, lam, P)) <= TOL_PARAM
+
+
+def test_method_mismatch_and_options(ff):
+    p = problem(3, 3, 4, 20, seed=1)
+    ctx = run_as(ff, p, 0)
+    with pytest.raises(ff.FcaError) as e:
+        ff.fca_em_iterate(ctx, 1)
+    assert e.value.status == ff.FCA_ERR_STATE
+    for key, val in [("K", 0), ("K", 65), ("path", 3), ("waves", 3), ("nope", 1)]:
+        with pytest.raises(ff.FcaError) as e:
+            ff.fca_set_option(ctx, key, val)
+        assert e.value.status == ff.FCA_ERR_ARG
+    with pytest.raises(ff.FcaError):
+        ff.fastfca_as_iterate(ctx, -1)
+
+
+def test_nonfinite_input_detected(ff):
+    """A NaN in the mixture propagates to the parameters and is reported when
+    the opt-in finiteness check is on (it is a host-forced condition: every
+    kernel still runs to completion)."""
+    p = problem(3, 3, 8, 40, seed=2)
+    p.x[3, 5, 1] = np.nan
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+    ff.fca_set_option(ctx, "check_finite", 1)
+    with pytest.raises(ff.FcaError) as e:
+        ff.fastfca_as_iterate(ctx, 1)
+    assert e.value.status == ff.FCA_ERR_NONFINITE
