@@ -1,0 +1,229 @@
+"""Throughput of FastFCA-AS against conventional FCA EM on one MI355X.
+
+A step is one whole separation job on the 10 s speech-scale workload
+(I = J = 3 microphones/sources, F = 513 bins, N = 626 frames, 100 hybrid
+iterations, complex64 data with FP32 arithmetic): reset the parameters to the
+seeded initial point, run the 100 iterations (Section 4.4 of the paper),
+evaluate the log-likelihood (eq. 14) and apply the multichannel Wiener filter
+(eq. 3).  Inputs are resident in device memory before timing starts.
+
+value = N * F * iterations / (seconds per step), in time-frequency-point
+iterations per second.  The same job with the conventional FCA EM algorithm
+(Section 3.3) is timed beside it on the same GPU, and the FP64 CPU oracle is
+timed on a bounded sample on the host.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+       python bench.py --calibrate-copy     (plain copy of a known size, for
+                                             scaling hardware byte counters)
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
+
+METRIC = "TF-point-iters/s: FastFCA-AS vs plain FCA EM, 1 GPU, I=J=3, F=513"
+
+
+def as_bytes_per_point_iter(I, J):
+    """Algorithmic HBM bytes of one FastFCA-AS iteration per time-frequency
+    point: read x (8I), read v (4J), write v (4J)."""
+    return 8 * I + 8 * J
+
+
+def as_flops_per_point_iter(I, J):
+    """Algorithmic FP32 operations of one hybrid iteration per point:
+    basis transform y = P^H x (8I^2), |y|^2 (3I), model variances, gains,
+    posterior statistics and the v update (11IJ), lambda sums (2IJ + J),
+    new variances and weights (2IJ + I), x x^H (3I + 3I(I-1)) and the I
+    weighted covariance sums (2I^3)."""
+    return 8 * I * I + 3 * I + 11 * I * J + 2 * I * J + J + 2 * I * J + I + 3 * I + 3 * I * (I - 1) + 2 * I ** 3
+
+
+def fca_em_flops_per_point_iter(I, J):
+    """Algorithmic FP32 operations of one conventional FCA EM iteration per
+    point (complex multiply-add = 8 flops): model covariance (2JI^2), one
+    Hermitian inverse (~4I^3 by Cholesky), per source the two products
+    S_j C^-1 and (S_j C^-1) S_j (8I^3 + 4I^3), mu_j (8I^2), Rhat (6I^2),
+    trace (4I^2) and the sum of eq. 10 (2I^2)."""
+    return 2 * J * I * I + 4 * I ** 3 + J * (12 * I ** 3 + 20 * I * I)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="speech10s")
+    ap.add_argument("--iters", type=int, default=None, help="override the workload's iteration count")
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--path", type=int, default=0)
+    ap.add_argument("--em-steps", type=int, default=3)
+    ap.add_argument("--no-em", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    n = 256 << 20
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "launches": 5}))
+
+
+def cpu_baseline(prob, iters_as=30, iters_em=5):
+    """The FP64 oracle as it stands, single-threaded, on the same rounded
+    inputs: a bounded number of iterations of each method."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    F, N, I, J = prob.shape
+    out = {}
+    with threadpool_limits(1):
+        v, lam, P = prob.v0, prob.lam0, prob.P0
+        t0 = time.perf_counter()
+        for _ in range(iters_as):
+            v, lam, P = oracle.fastfca_as_step(prob.x, v, lam, P)
+        t_as = time.perf_counter() - t0
+        R = oracle.as_spatial_cov(prob.P0, prob.lam0)
+        v = prob.v0
+        t0 = time.perf_counter()
+        for _ in range(iters_em):
+            v, R = oracle.fca_em_step(prob.x, v, R)
+        t_em = time.perf_counter() - t0
+    out["value"] = N * F * iters_as / t_as
+    out["unit"] = "TF-point-iters/s"
+    out["cores"] = 1
+    out["kind"] = "oracle"
+    out["sample"] = (f"FastFCA-AS oracle, {iters_as} of the workload's iterations on all {F} bins "
+                     f"({t_as:.1f} s); FCA EM oracle {iters_em} iterations ({t_em:.1f} s) -> "
+                     f"{N * F * iters_em / t_em:.4g} TF-point-iters/s; numpy FP64, 1 thread")
+    out["fca_em_value"] = N * F * iters_em / t_em
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the frequency bins shard across "
+                                   "GPUs without communication, but no multi-GPU run is implemented"}))
+        sys.exit(2)
+    import torch
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    from paper_1805_09498_amd import fastfca as ff
+    from paper_1805_09498_amd import synth
+
+    cfg = dict(synth.CONFIGS[args.config])
+    iters = args.iters or cfg["iters"]
+    I, J, F, N = cfg["I"], cfg["J"], cfg["F"], cfg["N"]
+    prob = synth.make_config(args.config).rounded_c64()
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(prob.x.astype(np.complex64)).to(dev)
+    v0 = torch.from_numpy(prob.v0.astype(np.float32)).to(dev)
+    lam0 = torch.from_numpy(prob.lam0.astype(np.float32)).to(dev)
+    P0 = torch.from_numpy(prob.P0.astype(np.complex64)).to(dev)
+    out = torch.empty((J, F, N, I), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed_job(method, n_steps, n_warm):
+        ctx = ff.fca_init(method, x, v0, lam0, P0)
+        if method == ff.FCA_METHOD_AS:
+            ff.fca_set_option(ctx, "waves", args.waves)
+            ff.fca_set_option(ctx, "path", args.path)
+            iterate = ff.fastfca_as_iterate
+            reset = (v0, lam0, P0)
+        else:
+            iterate = ff.fca_em_iterate
+            _, _, R_init = ff.fca_get_params(ctx)
+            reset = (v0, None, R_init.clone())
+        events = []
+
+        def step(record):
+            ff.fca_set_params(ctx, *reset)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            iterate(ctx, iters)
+            e1.record(stream)
+            L = ff.fca_loglik(ctx)       # synchronises the stream
+            ff.fca_wiener_separate(ctx, out)
+            if record:
+                events.append((e0, e1))
+            return L
+
+        for _ in range(n_warm):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            L = step(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+        ff.fca_destroy(ctx)
+        return (t1 - t0) * 1e3 / n_steps, it_ms, L
+
+    ms_as, it_ms_as, L_as = timed_job(ff.FCA_METHOD_AS, args.steps, args.warmup)
+    pts = N * F * iters
+    value = pts / (ms_as * 1e-3)
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TF-point-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_as,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: I={I}, J={J}, F={F}, N={N}, {iters} FastFCA-AS iterations "
+                               f"+ log-likelihood + Wiener filter per step, complex64",
+                   "I": I, "J": J, "F": F, "N": N, "iterations": iters, "parallelism": "1 GPU"},
+    }
+    # dominant kernel: the iteration launch(es) timed by events on the library's stream
+    flops = as_flops_per_point_iter(I, J) * pts
+    bytes_alg = as_bytes_per_point_iter(I, J) * pts
+    res["roofline"] = {
+        "bound": "alu",
+        "achieved": flops / (it_ms_as * 1e-3) / 1e12,
+        "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": flops / (it_ms_as * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+        "traffic": None,
+        "kernel": "k_as_resident (all iterations of one step in one launch)" if args.path != 2 else "k_as_pass_a/b + k_as_solve",
+        "kernel_ms": it_ms_as,
+        "algorithmic_GBps": bytes_alg / (it_ms_as * 1e-3) / 1e9,
+        "algorithmic_hbm_frac": bytes_alg / (it_ms_as * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+    res["loglik"] = L_as
+    if not args.no_em:
+        ms_em, it_ms_em, L_em = timed_job(ff.FCA_METHOD_EM, args.em_steps, 1)
+        v_em = pts / (ms_em * 1e-3)
+        res["fca_em"] = {"value": v_em, "ms_per_step": ms_em, "iterate_ms": it_ms_em, "loglik": L_em,
+                         "achieved_TFLOPs": fca_em_flops_per_point_iter(I, J) * pts / (it_ms_em * 1e-3) / 1e12}
+        res["speedup_vs_fca_em"] = value / v_em
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -307,21 +307,16 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
     }
   }
   __syncthreads();
-  float Lr[I][I], Li[I][I], dinv[I];
-  if (act) cholesky<I>(Qr, Qi, Lr, Li, dinv);
   for (int kk = 0; kk < s.K; ++kk) {
     float pr[I], pi[I];
     if (act) {
-      // b_i = column i of P^-H:  P^H b = e_i,  (P^H)_{rc} = conj(P_cr).
-      float Mr[I][I], Mi[I][I];
+      float Pr[I][I], Pi[I][I];
 #pragma unroll
-      for (int r = 0; r < I; ++r)
+      for (int a = 0; a < I; ++a)
 #pragma unroll
-        for (int c = 0; c < I; ++c) { Mr[r][c] = sPr[fl][c][r]; Mi[r][c] = -sPi[fl][c][r]; }
-#pragma unroll
-      for (int r = 0; r < I; ++r) { pr[r] = (r == i) ? 1.f : 0.f; pi[r] = 0.f; }
-      lu_solve<I>(Mr, Mi, pr, pi);
-      cholesky_solve<I>(Lr, Li, dinv, pr, pi);  // p_i = Q_i^-1 b_i
+        for (int b = 0; b < I; ++b) { Pr[a][b] = sPr[fl][a][b]; Pi[a][b] = sPi[fl][a][b]; }
+      pinvh_column<I>(Pr, Pi, i, pr, pi);   // b_i = column i of P^-H
+      herm_solve<I>(Qr, Qi, pr, pi);        // p_i = Q_i^-1 b_i
     }
     __syncthreads();
     if (act) {
