@@ -20,15 +20,14 @@ namespace fca {
 constexpr int kResMaxBlock = 256;
 constexpr int kResMaxWaves = kResMaxBlock / kWave;
 
-// Sum the per-wave partials part[w * stride + k], k < V, into part[k] (wave 0's
-// slot).  Needs a barrier before (partials written) and after (totals read).
-template <int V>
-__device__ __forceinline__ void combine_waves(float* part, int stride, int nw) {
-  for (int k = threadIdx.x; k < V; k += blockDim.x) {
-    float t = part[k];
-    for (int w = 1; w < nw; ++w) t += part[w * stride + k];
-    part[k] = t;
-  }
+// Sum of the per-wave partials part[w * stride + k] over the nw waves (the
+// loop is unrolled to the maximum wave count; nw is uniform).
+__device__ __forceinline__ float sum_waves(const float* part, int stride, int k, int nw) {
+  float t = part[k];
+#pragma unroll
+  for (int w = 1; w < kResMaxWaves; ++w)
+    if (w < nw) t += part[w * stride + k];
+  return t;
 }
 
 template <int I, int J, int NPT>
@@ -42,6 +41,9 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
   const int f = blockIdx.x;
   const int T = blockDim.x, nw = T / kWave;
   const int c = (int)(threadIdx.x % I);            // the column of eq. 23 this lane solves
+  // first frame of this wave's slot 0; a slot k is skipped by the whole wave
+  // when wbase + k T >= N (a scalar branch)
+  const int wbase = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) * kWave;
   __shared__ float sPr[I][I], sPi[I][I];
   __shared__ float sLam[J * I];
   __shared__ float redS[kResMaxWaves * VS];
@@ -88,10 +90,6 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
     for (int j = 0; j < J; ++j)
 #pragma unroll
       for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
-    // column c of P^-H for the fixed-point step; independent of phase A, so
-    // it is computed here where the scheduler can overlap it.
-    float br[I], bi[I];
-    pinvh_column<I>(Pr, Pi, c, br, bi);
 
     // ---- phase A: E-step statistics, v update, eq. 20 summands ------------
     {
@@ -107,7 +105,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
         for (int i = 0; i < I; ++i) S[j][i] = 0.f;
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        if (k * T < s.N) {  // uniform: skip slots no lane of the block owns
+        if (wbase + k * T < s.N) {  // wave-uniform: skip slots no lane of the wave owns
           const bool ok = threadIdx.x + k * T < s.N;
           float y2[I];
           as_transform_pow<I>(Pr, Pi, xr[k], xi[k], y2);
@@ -122,14 +120,10 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
       wave_totals_to_lds<J * I>(flat, redS, VS);
     }
     __syncthreads();
-    if (nw > 1) {
-      combine_waves<J * I>(redS, VS, nw);
-      __syncthreads();
-    }
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-      for (int i = 0; i < I; ++i) lam[j][i] = redS[j * I + i] * invN;  // eq. 20
+      for (int i = 0; i < I; ++i) lam[j][i] = sum_waves(redS, VS, j * I + i, nw) * invN;  // eq. 20
 
     // ---- phase B: weighted covariances of eq. 23 --------------------------
     if constexpr (kOnePass) {
@@ -140,7 +134,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
         for (int q = 0; q < I * I; ++q) A[i][q] = 0.f;
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        if (k * T < s.N) {
+        if (wbase + k * T < s.N) {
           const bool ok = threadIdx.x + k * T < s.N;
           float w[I];
           as_point_weights<I, J>(lam, v[k], w);
@@ -179,50 +173,54 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
         for (int q = 0; q < I * I; ++q) A[q] = 0.f;
 #pragma unroll
         for (int k = 0; k < NPT; ++k)
-          if (k * T < s.N) herm_rank1_acc<I>(A, w[k][i], xr[k], xi[k]);
+          if (wbase + k * T < s.N) herm_rank1_acc<I>(A, w[k][i], xr[k], xi[k]);
         wave_totals_to_lds<I * I>(A, redQ + i * VQ, QSTRIDE);
       }
     }
     __syncthreads();
-    if (nw > 1) {
-      combine_waves<QSTRIDE>(redQ, QSTRIDE, nw);
-      __syncthreads();
-    }
 
     // ---- per-bin solve: lane c < I computes column c of eq. 23 ------------
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int q = 0; q < J * I; ++q) sLam[q] = lam[q / I][q % I];
     }
-    float Qr[I][I], Qi[I][I];
-    {
+    // Wave 0 solves (lane c: column c); the other waves go straight to the
+    // barrier that publishes the new P.
+    if (wbase == 0) {
+      float Qr[I][I], Qi[I][I];
       const float* Qc = redQ + (kOnePass ? c * I * I : c * VQ);
 #pragma unroll
       for (int a = 0; a < I; ++a)
 #pragma unroll
         for (int b = a; b < I; ++b) {
-          Qr[a][b] = Qc[a * I + b] * invN;
-          Qi[a][b] = (b > a) ? Qc[b * I + a] * invN : 0.f;
+          Qr[a][b] = sum_waves(Qc, QSTRIDE, a * I + b, nw) * invN;
+          Qi[a][b] = (b > a) ? sum_waves(Qc, QSTRIDE, b * I + a, nw) * invN : 0.f;
         }
-    }
+      float br[I], bi[I];
+      pinvh_column<I>(Pr, Pi, c, br, bi);
+      herm_solve<I>(Qr, Qi, br, bi);  // p_c = Q_c^-1 [P^-H]_c
+      // K > 1: further fixed-point steps reuse Q_c; lane b holds column b of
+      // the current P, so the matrix is gathered with readlane (no LDS, no
+      // barrier: only wave 0 takes part).
 #pragma unroll 1
-    for (int kk = 0; kk < s.K; ++kk) {
-      if (kk > 0) {
+      for (int kk = 1; kk < s.K; ++kk) {
         float P2r[I][I], P2i[I][I];
 #pragma unroll
         for (int a = 0; a < I; ++a)
 #pragma unroll
-          for (int b = 0; b < I; ++b) { P2r[a][b] = sPr[a][b]; P2i[a][b] = sPi[a][b]; }
+          for (int b = 0; b < I; ++b) {
+            P2r[a][b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(br[a]), b));
+            P2i[a][b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bi[a]), b));
+          }
         pinvh_column<I>(P2r, P2i, c, br, bi);
+        herm_solve<I>(Qr, Qi, br, bi);
       }
-      herm_solve<I>(Qr, Qi, br, bi);  // p_c = Q_c^-1 [P^-H]_c
-      __syncthreads();
       if (threadIdx.x < I) {
 #pragma unroll
         for (int a = 0; a < I; ++a) { sPr[a][c] = br[a]; sPi[a][c] = bi[a]; }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 
   // ---- write the state back ------------------------------------------------
