@@ -236,11 +236,29 @@ fca_status fca_em_iterate(fca_ctx* c, int n_iter) {
   if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
   if (c->method != FCA_METHOD_EM) return fail(c, FCA_ERR_STATE, "fca_em_iterate on a FastFCA-AS context");
   if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
-  for (int it = 0; it < n_iter; ++it) {
-    hipError_t e = c->ks->em_iter(c->s, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "EM iteration");
+  if (n_iter == 0) return FCA_OK;
+  int waves = c->waves > 0 ? c->waves : 0;
+  if (!waves)
+    for (int w : {2, 1, 4})
+      if (c->ks->em_resident_fits(c->N, w)) { waves = w; break; }
+  if (!waves) waves = 4;
+  const bool resident = c->path == 1 || (c->path == 0 && c->ks->em_resident_fits(c->N, waves));
+  if (resident) {
+    if (!c->ks->em_resident_fits(c->N, waves))
+      return fail(c, FCA_ERR_ARG, "the frequency-resident EM path does not fit this (I, J, N) with this wave count");
+    for (int done = 0; done < n_iter;) {
+      const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
+      hipError_t e = c->ks->em_iter_resident(c->s, c->stream, step, waves);
+      if (e != hipSuccess) return hip_fail(c, e, "resident EM iteration");
+      done += step;
+    }
+  } else {
+    for (int it = 0; it < n_iter; ++it) {
+      hipError_t e = c->ks->em_iter(c->s, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "EM iteration");
+    }
   }
-  return n_iter ? post_check(c) : FCA_OK;
+  return post_check(c);
 }
 
 fca_status fca_wiener_separate(fca_ctx* c, fca_c64* out) {

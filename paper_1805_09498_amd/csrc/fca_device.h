@@ -389,4 +389,34 @@ __device__ __forceinline__ void herm_solve(const float (&Qr)[I][I], const float 
   }
 }
 
+// Inverse of a Hermitian positive-definite matrix given by its upper triangle
+// (full result in Xr/Xi).  I <= 3: adjugate / determinant; larger I:
+// Cholesky.
+template <int I>
+__device__ __forceinline__ void herm_inv(const float (&Ar)[I][I], const float (&Ai)[I][I],
+                                         float (&Xr)[I][I], float (&Xi)[I][I]) {
+  if constexpr (I == 1) {
+    Xr[0][0] = rcp(Ar[0][0]); Xi[0][0] = 0.f;
+  } else if constexpr (I == 2) {
+    const float a = Ar[0][0], d = Ar[1][1], xr = Ar[0][1], xi = Ai[0][1];
+    const float id = rcp(a * d - (xr * xr + xi * xi));
+    Xr[0][0] = d * id; Xi[0][0] = 0.f; Xr[1][1] = a * id; Xi[1][1] = 0.f;
+    Xr[0][1] = -xr * id; Xi[0][1] = -xi * id; Xr[1][0] = -xr * id; Xi[1][0] = xi * id;
+  } else if constexpr (I == 3) {
+    const float a = Ar[0][0], d = Ar[1][1], g = Ar[2][2];
+    const float xr = Ar[0][1], xi = Ai[0][1], yr = Ar[0][2], yi = Ai[0][2], zr = Ar[1][2], zi = Ai[1][2];
+    const float A00 = d * g - (zr * zr + zi * zi), A11 = a * g - (yr * yr + yi * yi), A22 = a * d - (xr * xr + xi * xi);
+    const float A01r = (yr * zr + yi * zi) - xr * g, A01i = (yi * zr - yr * zi) - xi * g;
+    const float A02r = (xr * zr - xi * zi) - yr * d, A02i = (xr * zi + xi * zr) - yi * d;
+    const float A12r = (yr * xr + yi * xi) - a * zr, A12i = (yi * xr - yr * xi) - a * zi;
+    const float id = rcp(a * A00 + (xr * A01r + xi * A01i) + (yr * A02r + yi * A02i));
+    Xr[0][0] = A00 * id; Xi[0][0] = 0.f; Xr[1][1] = A11 * id; Xi[1][1] = 0.f; Xr[2][2] = A22 * id; Xi[2][2] = 0.f;
+    Xr[0][1] = A01r * id; Xi[0][1] = A01i * id; Xr[1][0] = A01r * id; Xi[1][0] = -A01i * id;
+    Xr[0][2] = A02r * id; Xi[0][2] = A02i * id; Xr[2][0] = A02r * id; Xi[2][0] = -A02i * id;
+    Xr[1][2] = A12r * id; Xi[1][2] = A12i * id; Xr[2][1] = A12r * id; Xi[2][1] = -A12i * id;
+  } else {
+    herm_inverse<I>(Ar, Ai, Xr, Xi);
+  }
+}
+
 }  // namespace fca

@@ -547,31 +547,18 @@ __device__ __forceinline__ void em_model_cov(const EmShared<I, J>& sh, const flo
     }
 }
 
-// One EM point: E-step (eq. 7-8) for every j, v update (eq. 9), summand of
-// eq. 10 reduced over the wave into the wave's LDS accumulator.
+// One FCA EM point: E-step (eq. 7-8) for every source with one Hermitian
+// inverse C^-1 and two I x I products per source (S_j C^-1 and (S_j C^-1) S_j),
+// the v update (eq. 9, current S_j) and the summand of eq. 10 (new v_j),
+// Rhat_j / v_j in packed Hermitian slots, added to H[j] (nothing if !ok).
 template <int I, int J>
-__global__ __launch_bounds__(kBlock) void k_em_pass(DevState s) {
-  const int f = blockIdx.y, chunk = blockIdx.x;
-  __shared__ EmShared<I, J> sh;
-  __shared__ float acc[kBlock / kWave][J][I * I];
-  em_load_shared<I, J>(s, f, sh);
-  for (int t = threadIdx.x; t < (kBlock / kWave) * J * I * I; t += kBlock) (&acc[0][0][0])[t] = 0.f;
-  __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int n = chunk * kChunkEm + threadIdx.x;
-  const bool ok = n < s.N;
-  const int nn = ok ? n : 0;
-  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
-  float* vf = s.vs + (size_t)f * J * s.Npad;
-  float xr[I], xi[I], v[J];
-#pragma unroll
-  for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
-#pragma unroll
-  for (int j = 0; j < J; ++j) v[j] = ok ? vf[(size_t)j * s.Npad + nn] : 1.f;
+__device__ __forceinline__ void em_point(const EmShared<I, J>& sh, const float (&xr)[I],
+                                         const float (&xi)[I], float (&v)[J], float (&H)[J][I * I],
+                                         bool ok) {
   float Cr[I][I], Ci[I][I], Xr[I][I], Xi[I][I];
   em_model_cov<I, J>(sh, v, Cr, Ci);
-  herm_inverse<I>(Cr, Ci, Xr, Xi);  // C^-1 (one inversion per point)
-#pragma unroll 1
+  herm_inv<I>(Cr, Ci, Xr, Xi);  // C^-1 (one inversion per point)
+#pragma unroll
   for (int j = 0; j < J; ++j) {
     // K = S_j C^-1 (first product); W_j = v_j K.
     float Kr[I][I], Ki[I][I];
@@ -627,28 +614,60 @@ __global__ __launch_bounds__(kBlock) void k_em_pass(DevState s) {
       for (int b = a + 1; b < I; ++b)
         tr = fmaf(2.f, fmaf(sh.Sr[j][a][b], Hr[a][b], sh.Si[j][a][b] * Hi[a][b]), tr);
     }
-    const float vn = tr / float(I);
-    if (ok) vf[(size_t)j * s.Npad + n] = vn;
-    const float iv = ok ? 1.0f / vn : 0.f;
-    // summand of eq. 10 (with the new v_j), packed Hermitian slots
+    const float vn = tr * (1.0f / float(I));
+    v[j] = ok ? vn : v[j];
+    const float iv = ok ? rcp(vn) : 0.f;
 #pragma unroll
     for (int a = 0; a < I; ++a)
 #pragma unroll
       for (int b = a; b < I; ++b) {
-        const float t1 = wave_sum(Hr[a][b] * iv);
-        if (lane == 0) acc[wave][j][a * I + b] += t1;
-        if (b > a) {
-          const float t2 = wave_sum(Hi[a][b] * iv);
-          if (lane == 0) acc[wave][j][b * I + a] += t2;
-        }
+        H[j][a * I + b] = fmaf(Hr[a][b], iv, H[j][a * I + b]);
+        if (b > a) H[j][b * I + a] = fmaf(Hi[a][b], iv, H[j][b * I + a]);
       }
   }
+}
+
+// Streaming FCA EM pass: one point per lane; per source the summands of
+// eq. 10 are summed over the wave (transposed reduction) into the wave's LDS
+// slot, then over the waves into the tile partial.
+template <int I, int J>
+__global__ __launch_bounds__(kBlock) void k_em_pass(DevState s) {
+  constexpr int V = pad4(I * I);
+  const int f = blockIdx.y, chunk = blockIdx.x;
+  __shared__ EmShared<I, J> sh;
+  __shared__ float acc[kBlock / kWave][J][V];
+  em_load_shared<I, J>(s, f, sh);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  const int n = chunk * kChunkEm + threadIdx.x;
+  const bool ok = n < s.N;
+  const int nn = ok ? n : 0;
+  const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
+  float* vf = s.vs + (size_t)f * J * s.Npad;
+  float xr[I], xi[I], v[J];
+#pragma unroll
+  for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
+#pragma unroll
+  for (int j = 0; j < J; ++j) v[j] = ok ? vf[(size_t)j * s.Npad + nn] : 1.f;
+  float H[J][I * I];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int q = 0; q < I * I; ++q) H[j][q] = 0.f;
+  em_point<I, J>(sh, xr, xi, v, H, ok);
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[j];
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) wave_totals_to_lds<I * I>(H[j], &acc[0][j][0], J * V);
   __syncthreads();
   float* out = s.partA + ((size_t)f * s.nchunk_em + chunk) * J * I * I;
   for (int t = threadIdx.x; t < J * I * I; t += kBlock) {
+    const int j = t / (I * I), q = t % (I * I);
     float u = 0.f;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) u += (&acc[w][0][0])[t];
+    for (int w = 0; w < kBlock / kWave; ++w) u += acc[w][j][q];
     out[t] = u;
   }
 }
@@ -679,7 +698,7 @@ __global__ void k_em_finalize(DevState s) {
       Rr[b][a] = Rr[a][b]; Ri[b][a] = -Ri[a][b];
     }
   }
-  herm_inverse<I>(Rr, Ri, Xr, Xi);
+  herm_inv<I>(Rr, Ri, Xr, Xi);
   float2* R = s.R + ((size_t)f * J + j) * I * I;
   float2* X = s.Rinv + ((size_t)f * J + j) * I * I;
 #pragma unroll
@@ -769,7 +788,7 @@ __global__ void k_em_rinv(DevState s) {
       Rr[a][b] = r.x; Ri[a][b] = (a == b) ? 0.f : r.y;
       Rr[b][a] = r.x; Ri[b][a] = -Ri[a][b];
     }
-  herm_inverse<I>(Rr, Ri, Xr, Xi);
+  herm_inv<I>(Rr, Ri, Xr, Xi);
   float2* X = s.Rinv + ((size_t)f * J + j) * I * I;
 #pragma unroll
   for (int a = 0; a < I; ++a)

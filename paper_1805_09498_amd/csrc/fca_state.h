@@ -44,6 +44,8 @@ struct KernelSet {
   hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
   int (*as_resident_fits)(int N, int waves);
   hipError_t (*em_iter)(const DevState&, hipStream_t);
+  hipError_t (*em_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
+  int (*em_resident_fits)(int N, int waves);
   hipError_t (*as_loglik)(const DevState&, hipStream_t);
   hipError_t (*em_loglik)(const DevState&, hipStream_t);
   hipError_t (*as_wiener)(const DevState&, hipStream_t, float2* out);

@@ -43,13 +43,15 @@ def test_as_edge_shapes(ff, I, J, F, N):
 @pytest.mark.parametrize("I,J,F,N", CASES)
 def test_em_edge_shapes(ff, I, J, F, N):
     p = problem(I, J, F, N, seed=100 * I + 10 * J + F)
-    t = to_dev(p)
-    ctx = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"])
-    ff.fca_em_iterate(ctx, 1)
-    v, _, R = params(ff, ctx)
     v_ref, R_ref = oracle_em(p, oracle.as_spatial_cov(p.P0, p.lam0), 1)
-    assert rel(v, v_ref) <= TOL_PARAM
-    assert rel(R, R_ref) <= TOL_PARAM
+    for path in (0, 2):
+        t = to_dev(p)
+        ctx = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"])
+        ff.fca_set_option(ctx, "path", path)
+        ff.fca_em_iterate(ctx, 1)
+        v, _, R = params(ff, ctx)
+        assert rel(v, v_ref) <= TOL_PARAM, (path, rel(v, v_ref))
+        assert rel(R, R_ref) <= TOL_PARAM, (path, rel(R, R_ref))
 
 
 @pytest.mark.parametrize("I,J,F,N", [(1, 2, 4, 7), (2, 3, 7, 65), (8, 9, 2, 700), (6, 7, 3, 2049)])

@@ -24,19 +24,21 @@ def c64(a):
     return a.astype(np.complex64).astype(np.complex128)
 
 
-def run_em(ff, p, n_iter, R0=None):
+def run_em(ff, p, n_iter, R0=None, path=0):
     t = to_dev(p, R0)
     ctx = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"], t.get("R0"))
+    ff.fca_set_option(ctx, "path", path)
     ff.fca_em_iterate(ctx, n_iter)
     return ctx
 
 
 @pytest.mark.parametrize("cfg", [dict(I=3, J=3, F=129, N=100, seed=1000),
                                  dict(I=3, J=3, F=513, N=626, seed=2000)], ids=["small", "speech10s"])
-def test_one_iteration_from_as_start(ff, cfg):
+@pytest.mark.parametrize("path", [1, 2], ids=["resident", "streaming"])
+def test_one_iteration_from_as_start(ff, cfg, path):
     """EM context started at S_j = P^-H diag(lambda_j) P^-1, formed on the device."""
     p = problem(**cfg)
-    ctx = run_em(ff, p, 1)
+    ctx = run_em(ff, p, 1, path=path)
     v, _, R = params(ff, ctx)
     v_ref, R_ref = oracle_em(p, oracle.as_spatial_cov(p.P0, p.lam0), 1)
     print(rel(v, v_ref), rel(R, R_ref))
@@ -56,9 +58,10 @@ def test_one_iteration_given_covariances(ff):
 
 @pytest.mark.parametrize("cfg", [dict(I=3, J=3, F=129, N=100, seed=1000),
                                  dict(I=3, J=3, F=513, N=626, seed=2000)], ids=["small", "speech10s"])
-def test_ten_iterations_loglik(ff, cfg):
+@pytest.mark.parametrize("path", [1, 2], ids=["resident", "streaming"])
+def test_ten_iterations_loglik(ff, cfg, path):
     p = problem(**cfg)
-    ctx = run_em(ff, p, 10)
+    ctx = run_em(ff, p, 10, path=path)
     L = ff.fca_loglik(ctx)
     v_ref, R_ref = oracle_em(p, oracle.as_spatial_cov(p.P0, p.lam0), 10)
     L_ref = oracle.loglik_fca(p.x, v_ref, R_ref)
