@@ -58,6 +58,31 @@ def fca_em_flops_per_point_iter(I, J):
     return 2 * J * I * I + 4 * I ** 3 + J * (12 * I ** 3 + 20 * I * I)
 
 
+KERNEL_SOURCES = ("fca_resident.h", "fca_kernels.h", "fca_device.h", "fca_state.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_as_resident_speech10s_traffic.txt")
+
+
+def profiled_traffic(workload, shape):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
+    changed since the counters were taken (source hash), or the workload or
+    launch shape differ from the profiled ones."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_FILE).read().splitlines()
+                      if ": " in line and not line.startswith(" "))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1805_09498_amd", "csrc", f), "rb").read())
+    want_shape = f"waves={shape['waves_per_workgroup']} bins_per_wg={shape['bins_per_workgroup']}"
+    if (fields.get("source_sha256") != h.hexdigest() or fields.get("workload") != workload
+            or fields.get("launch_shape") != want_shape):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +91,8 @@ def parse():
     ap.add_argument("--config", default="speech10s")
     ap.add_argument("--iters", type=int, default=None, help="override the workload's iteration count")
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--bins-per-wg", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--em-steps", type=int, default=3)
     ap.add_argument("--no-em", action="store_true")
@@ -144,7 +171,9 @@ def main():
         ctx = ff.fca_init(method, x, v0, lam0, P0)
         if method == ff.FCA_METHOD_AS:
             ff.fca_set_option(ctx, "waves", args.waves)
+            ff.fca_set_option(ctx, "bins_per_wg", args.bins_per_wg)
             ff.fca_set_option(ctx, "path", args.path)
+            ff.fca_set_option(ctx, "autotune", args.autotune)
             iterate = ff.fastfca_as_iterate
             reset = (v0, lam0, P0)
         else:
@@ -175,10 +204,12 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         it_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+        shape = {"waves_per_workgroup": ff.fca_get_option(ctx, "last_waves"),
+                 "bins_per_workgroup": ff.fca_get_option(ctx, "last_bins_per_wg")}
         ff.fca_destroy(ctx)
-        return (t1 - t0) * 1e3 / n_steps, it_ms, L
+        return (t1 - t0) * 1e3 / n_steps, it_ms, L, shape
 
-    ms_as, it_ms_as, L_as = timed_job(ff.FCA_METHOD_AS, args.steps, args.warmup)
+    ms_as, it_ms_as, L_as, shape_as = timed_job(ff.FCA_METHOD_AS, args.steps, args.warmup)
     pts = N * F * iters
     value = pts / (ms_as * 1e-3)
     res = {
@@ -208,16 +239,21 @@ def main():
         "unit": "TFLOP/s",
         "frac": flops / (it_ms_as * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
         "traffic": None,
-        "kernel": "k_as_resident (all iterations of one step in one launch)" if args.path != 2 else "k_as_pass_a/b + k_as_solve",
+        "kernel": ("k_as_resident (frequency-resident; all iterations of a step in one launch)"
+                   if args.path != 2 else "k_as_pass_a + k_as_pass_b + k_as_solve per iteration"),
         "kernel_ms": it_ms_as,
         "algorithmic_GBps": bytes_alg / (it_ms_as * 1e-3) / 1e9,
         "algorithmic_hbm_frac": bytes_alg / (it_ms_as * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
+    res["roofline"]["launch_shape"] = shape_as
+    if args.path != 2 and iters <= 1024:
+        res["roofline"]["traffic"] = profiled_traffic(args.config, shape_as)
     res["loglik"] = L_as
     if not args.no_em:
-        ms_em, it_ms_em, L_em = timed_job(ff.FCA_METHOD_EM, args.em_steps, 1)
+        ms_em, it_ms_em, L_em, shape_em = timed_job(ff.FCA_METHOD_EM, args.em_steps, 1)
         v_em = pts / (ms_em * 1e-3)
         res["fca_em"] = {"value": v_em, "ms_per_step": ms_em, "iterate_ms": it_ms_em, "loglik": L_em,
+                         "launch_shape": shape_em,
                          "achieved_TFLOPs": fca_em_flops_per_point_iter(I, J) * pts / (it_ms_em * 1e-3) / 1e12}
         res["speedup_vs_fca_em"] = value / v_em
     if not args.no_cpu_baseline:

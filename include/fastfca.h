@@ -126,9 +126,24 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * FCA_ERR_NONFINITE if a parameter is NaN/Inf), "path" (0 = automatic,
  * 1 = force the frequency-resident kernels, 2 = force the streaming
  * kernels), "waves" (64-lane waves per workgroup of the frequency-resident
- * kernel: 0 = automatic, 1, 2 or 4).  Unknown keys or values out of range
- * give FCA_ERR_ARG. */
+ * kernels: 0 = automatic, 1, 2 or 4), "bins_per_wg" (frequency bins per
+ * workgroup of the frequency-resident FastFCA-AS kernel: 0 = automatic, 1 or
+ * 2; 2 needs at least 2 waves), "autotune" (1 = default: unless a shape is
+ * forced by the options above, the first iterate call of a context times
+ * every launch shape that fits on a saved copy of the state, restores it and
+ * caches the fastest for the process under (method, I, J, F, N); this call
+ * synchronises the stream.  0 = fixed preference order).  Unknown keys or
+ * values out of range give FCA_ERR_ARG; a forced shape that cannot hold N
+ * frames per bin makes the iterate call return FCA_ERR_ARG.  Results are
+ * bitwise reproducible for a given launch shape. */
 fca_status fca_set_option(fca_ctx *ctx, const char *key, long long value);
+
+/* Read an option ("K", "check_finite", "path", "waves", "bins_per_wg",
+ * "autotune": the configured values) or the launch shape the last iterate
+ * call used ("last_waves": waves per workgroup, 0 = streaming kernels, -1 =
+ * no call yet; "last_bins_per_wg").  value is a host pointer.  Unknown keys
+ * give FCA_ERR_ARG. */
+fca_status fca_get_option(fca_ctx *ctx, const char *key, long long *value);
 
 /* Human-readable message for the last error on ctx, or for the calling
  * thread's last failed fca_init when ctx is NULL.  Never NULL. */

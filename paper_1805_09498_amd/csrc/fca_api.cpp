@@ -6,8 +6,11 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 
 #include "fca_state.h"
 
@@ -44,6 +47,10 @@ struct fca_ctx {
   int check_finite;
   int path;   // 0 auto, 1 resident, 2 streaming
   int waves;  // 0 auto
+  int bpw;    // bins per workgroup of the resident AS kernel, 0 auto
+  int autotune;  // 1: time the candidate launch shapes once per (method, I, J, F, N)
+  float* backup;  // state copy used while tuning: vs, lam, P (AS) or vs, R (EM)
+  int last_waves, last_bpw;  // launch shape of the last iterate call (waves 0: streaming)
   std::string err;
 };
 
@@ -74,15 +81,153 @@ struct Arena {
   }
 };
 
-// Waves per workgroup of the frequency-resident kernel when not forced by the
-// "waves" option: two 64-lane waves per bin when the bin fits (measured best
-// at the 10 s speech shape; one wave leaves half the SIMDs idle, four waves
-// spend more on cross-wave sums than they save), else the smallest that fits.
-int auto_waves(const fca_ctx* c) {
-  if (c->waves > 0) return c->waves;
-  for (int w : {2, 1, 4})
-    if (c->ks->as_resident_fits(c->N, w)) return w;
-  return 4;
+// ---------------------------------------------------------------------------
+// Launch shapes and the tuner.
+//
+// A shape is (waves per workgroup, bins per workgroup) of a frequency-resident
+// kernel, or the streaming path (waves = 0).  Which one is fastest depends on
+// F (bins against the 256 CUs: the dispatcher spreads 4-wave workgroups one
+// per CU but can double 2-wave ones up on a SIMD), N (frames per lane) and
+// (I, J) (registers).  With "autotune" on (the default) and no shape forced
+// by options, the first iterate call of a context times every shape that
+// fits on a saved copy of the state, restores the state and caches the
+// winner for the process under (method, I, J, F, N).
+// ---------------------------------------------------------------------------
+struct Shape {
+  int waves, bpw;  // waves == 0: streaming kernels
+};
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, Shape> g_tuned;
+
+bool shape_fits(const fca_ctx* c, Shape sh) {
+  if (sh.waves == 0) return true;
+  return c->method == FCA_METHOD_AS ? c->ks->as_resident_fits(c->N, sh.waves, sh.bpw) != 0
+                                    : (sh.bpw == 1 && c->ks->em_resident_fits(c->N, sh.waves) != 0);
+}
+
+hipError_t launch_shape(fca_ctx* c, Shape sh, int n_iter) {
+  if (sh.waves == 0) {
+    for (int it = 0; it < n_iter; ++it) {
+      hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_iter_stream(c->s, c->stream)
+                                                : c->ks->em_iter(c->s, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  for (int done = 0; done < n_iter;) {
+    const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
+    hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_iter_resident(c->s, c->stream, step, sh.waves, sh.bpw)
+                                              : c->ks->em_iter_resident(c->s, c->stream, step, sh.waves);
+    if (e != hipSuccess) return e;
+    done += step;
+  }
+  return hipSuccess;
+}
+
+// Byte sizes of the iterated state (backup layout: vs, then lam and P for
+// AS, R and Rinv for EM).
+size_t state_bytes_v(const fca_ctx* c) { return sizeof(float) * (size_t)c->F * c->J * c->s.Npad; }
+size_t state_bytes_p(const fca_ctx* c) {
+  return c->method == FCA_METHOD_AS ? sizeof(float2) * (size_t)c->F * c->I * c->I : 0;
+}
+
+hipError_t copy_one(fca_ctx* c, void* dev, char* bk, size_t n, bool save) {
+  return save ? hipMemcpyAsync(bk, dev, n, hipMemcpyDeviceToDevice, c->stream)
+              : hipMemcpyAsync(dev, bk, n, hipMemcpyDeviceToDevice, c->stream);
+}
+
+// Save the iterated state to the backup region or restore it from there.
+hipError_t copy_state(fca_ctx* c, bool save) {
+  char* b = reinterpret_cast<char*>(c->backup);
+  const size_t nv = state_bytes_v(c);
+  hipError_t e = copy_one(c, c->s.vs, b, nv, save);
+  if (c->method == FCA_METHOD_AS) {
+    const size_t nl = sizeof(float) * (size_t)c->F * c->J * c->I;
+    if (e == hipSuccess) e = copy_one(c, c->s.lam, b + nv, nl, save);
+    if (e == hipSuccess) e = copy_one(c, c->s.P, b + nv + nl, state_bytes_p(c), save);
+  } else {
+    const size_t nr = sizeof(float2) * (size_t)c->F * c->J * c->I * c->I;
+    if (e == hipSuccess) e = copy_one(c, c->s.R, b + nv, nr, save);
+    if (e == hipSuccess) e = copy_one(c, c->s.Rinv, b + nv + nr, nr, save);
+  }
+  return e;
+}
+
+// The launch shape for the next iterate call (may run the tuner).
+fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
+  static const Shape as_cands[] = {{1, 1}, {2, 1}, {4, 1}, {2, 2}, {4, 2}, {0, 0}};
+  static const Shape em_cands[] = {{1, 1}, {2, 1}, {4, 1}, {0, 0}};
+  const bool as = c->method == FCA_METHOD_AS;
+  const Shape* cands = as ? as_cands : em_cands;
+  const int ncand = as ? 6 : 4;
+  // Forced choices first.
+  if (c->path == 2) { *out = Shape{0, 0}; return FCA_OK; }
+  const bool forced = c->waves > 0 || c->bpw > 0;
+  if (forced || !c->autotune) {
+    for (int k = 0; k < ncand; ++k) {
+      Shape sh = cands[k];
+      if (sh.waves == 0) continue;
+      if (c->waves > 0) sh.waves = c->waves;
+      if (c->bpw > 0) sh.bpw = c->bpw;
+      if (shape_fits(c, sh)) { *out = sh; return FCA_OK; }
+    }
+    if (c->path == 1)
+      return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this N with this launch shape");
+    *out = Shape{0, 0};
+    return FCA_OK;
+  }
+  const auto key = std::make_tuple((int)c->method, c->I, c->J, c->F, c->N);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end() && (c->path == 0 || it->second.waves > 0)) { *out = it->second; return FCA_OK; }
+  }
+  // Tune: for each fitting shape, the marginal cost per iteration
+  // (T(n1 + n2) - T(n1)) / n2 (best of two trials each, from the saved state)
+  // projected to a call of max(n_iter, 20) iterations plus the fixed cost.
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(c, e, "tuner events");
+  if ((e = copy_state(c, true)) != hipSuccess) return hip_fail(c, e, "tuner save");
+  const int n1 = 8, n2 = 32;
+  const int nref = n_iter_hint > 20 ? n_iter_hint : 20;
+  float best = 1e30f;
+  Shape best_sh{0, 0};
+  for (int k = 0; k < ncand && e == hipSuccess; ++k) {
+    const Shape sh = cands[k];
+    if (!shape_fits(c, sh) || (c->path == 1 && sh.waves == 0)) continue;
+    float t[2] = {1e30f, 1e30f};
+    for (int len = 0; len < 2 && e == hipSuccess; ++len) {
+      for (int trial = 0; trial < 2 && e == hipSuccess; ++trial) {
+        if ((e = copy_state(c, false)) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+        if ((e = launch_shape(c, sh, len ? n1 + n2 : n1)) != hipSuccess) break;
+        if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (ms < t[len]) t[len] = ms;
+      }
+    }
+    if (e != hipSuccess) break;
+    float per = (t[1] - t[0]) / (float)n2;
+    if (per < 0.f) per = 0.f;
+    const float fixed = t[0] - n1 * per;
+    const float cost = fixed + nref * per;
+    if (cost < best) { best = cost; best_sh = sh; }
+  }
+  if (e == hipSuccess) e = copy_state(c, false);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "tuner run");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (c->path == 0) g_tuned[key] = best_sh;
+  }
+  *out = best_sh;
+  return FCA_OK;
 }
 
 fca_status post_check(fca_ctx* c) {
@@ -135,7 +280,8 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   if (!c) return fail(nullptr, FCA_ERR_HIP, "host allocation failed");
   c->method = method; c->F = F; c->N = N; c->I = I; c->J = J;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->arena = nullptr;
+  c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
+  c->backup = nullptr; c->arena = nullptr; c->last_waves = -1; c->last_bpw = -1;
 
   DevState& s = c->s;
   s.F = F; s.N = N; s.Npad = (int)Npad; s.K = 1;
@@ -159,6 +305,9 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   const size_t o_llf = a.take<double>(F);
   const size_t o_ll = a.take<double>(1);
   const size_t o_flag = a.take<int>(1);
+  // state backup for the tuner: vs, then lam (AS) or R and Rinv (EM), then P
+  const size_t o_bk = a.take<char>(sizeof(float) * (size_t)F * J * Npad +
+                                   (em ? 2 * sizeof(float2) * FJII : sizeof(float) * FJI + sizeof(float2) * FII));
   hipError_t e = hipMalloc(&c->arena, a.off);
   if (e != hipSuccess) {
     delete c;
@@ -178,6 +327,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   s.llf = reinterpret_cast<double*>(base + o_llf);
   s.ll = reinterpret_cast<double*>(base + o_ll);
   s.flag = reinterpret_cast<int*>(base + o_flag);
+  c->backup = reinterpret_cast<float*>(base + o_bk);
 
   hipStream_t st = c->stream;
   if ((e = fca::launch_pack_x(reinterpret_cast<const float2*>(x), const_cast<float*>(s.xs), F, N, I, s.Npad, st)) != hipSuccess ||
@@ -212,23 +362,12 @@ fca_status fastfca_as_iterate(fca_ctx* c, int n_iter) {
   if (c->method != FCA_METHOD_AS) return fail(c, FCA_ERR_STATE, "fastfca_as_iterate on an FCA EM context");
   if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
   if (n_iter == 0) return FCA_OK;
-  const int waves = auto_waves(c);
-  const bool resident = c->path == 1 || (c->path == 0 && c->ks->as_resident_fits(c->N, waves));
-  if (resident) {
-    if (!c->ks->as_resident_fits(c->N, waves))
-      return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this N with this wave count");
-    for (int done = 0; done < n_iter;) {
-      const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
-      hipError_t e = c->ks->as_iter_resident(c->s, c->stream, step, waves);
-      if (e != hipSuccess) return hip_fail(c, e, "resident iteration");
-      done += step;
-    }
-  } else {
-    for (int it = 0; it < n_iter; ++it) {
-      hipError_t e = c->ks->as_iter_stream(c->s, c->stream);
-      if (e != hipSuccess) return hip_fail(c, e, "streaming iteration");
-    }
-  }
+  Shape sh;
+  fca_status st = choose_shape(c, n_iter, &sh);
+  if (st != FCA_OK) return st;
+  c->last_waves = sh.waves; c->last_bpw = sh.bpw;
+  hipError_t e = launch_shape(c, sh, n_iter);
+  if (e != hipSuccess) return hip_fail(c, e, "FastFCA-AS iteration");
   return post_check(c);
 }
 
@@ -237,27 +376,12 @@ fca_status fca_em_iterate(fca_ctx* c, int n_iter) {
   if (c->method != FCA_METHOD_EM) return fail(c, FCA_ERR_STATE, "fca_em_iterate on a FastFCA-AS context");
   if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
   if (n_iter == 0) return FCA_OK;
-  int waves = c->waves > 0 ? c->waves : 0;
-  if (!waves)
-    for (int w : {2, 1, 4})
-      if (c->ks->em_resident_fits(c->N, w)) { waves = w; break; }
-  if (!waves) waves = 4;
-  const bool resident = c->path == 1 || (c->path == 0 && c->ks->em_resident_fits(c->N, waves));
-  if (resident) {
-    if (!c->ks->em_resident_fits(c->N, waves))
-      return fail(c, FCA_ERR_ARG, "the frequency-resident EM path does not fit this (I, J, N) with this wave count");
-    for (int done = 0; done < n_iter;) {
-      const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
-      hipError_t e = c->ks->em_iter_resident(c->s, c->stream, step, waves);
-      if (e != hipSuccess) return hip_fail(c, e, "resident EM iteration");
-      done += step;
-    }
-  } else {
-    for (int it = 0; it < n_iter; ++it) {
-      hipError_t e = c->ks->em_iter(c->s, c->stream);
-      if (e != hipSuccess) return hip_fail(c, e, "EM iteration");
-    }
-  }
+  Shape sh;
+  fca_status st = choose_shape(c, n_iter, &sh);
+  if (st != FCA_OK) return st;
+  c->last_waves = sh.waves; c->last_bpw = sh.bpw;
+  hipError_t e = launch_shape(c, sh, n_iter);
+  if (e != hipSuccess) return hip_fail(c, e, "FCA EM iteration");
   return post_check(c);
 }
 
@@ -339,9 +463,30 @@ fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
     if (value != 0 && value != 1 && value != 2 && value != 4)
       return fail(c, FCA_ERR_ARG, "waves must be 0 (auto), 1, 2 or 4");
     c->waves = (int)value;
+  } else if (!std::strcmp(key, "bins_per_wg")) {
+    if (value < 0 || value > 2) return fail(c, FCA_ERR_ARG, "bins_per_wg must be 0 (auto), 1 or 2");
+    c->bpw = (int)value;
+  } else if (!std::strcmp(key, "autotune")) {
+    if (value != 0 && value != 1) return fail(c, FCA_ERR_ARG, "autotune must be 0 or 1");
+    c->autotune = (int)value;
   } else {
     return fail(c, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
   }
+  return FCA_OK;
+}
+
+fca_status fca_get_option(fca_ctx* c, const char* key, long long* value) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!key || !value) return fail(c, FCA_ERR_ARG, "NULL key or value");
+  if (!std::strcmp(key, "K")) *value = c->s.K;
+  else if (!std::strcmp(key, "check_finite")) *value = c->check_finite;
+  else if (!std::strcmp(key, "path")) *value = c->path;
+  else if (!std::strcmp(key, "waves")) *value = c->waves;
+  else if (!std::strcmp(key, "bins_per_wg")) *value = c->bpw;
+  else if (!std::strcmp(key, "autotune")) *value = c->autotune;
+  else if (!std::strcmp(key, "last_waves")) *value = c->last_waves;
+  else if (!std::strcmp(key, "last_bins_per_wg")) *value = c->last_bpw;
+  else return fail(c, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
   return FCA_OK;
 }
 

@@ -31,29 +31,40 @@ __device__ __forceinline__ float sum_waves(const float* part, int stride, int k,
 }
 
 template <int I, int J, int NPT>
-__global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_iter) {
+__global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_iter, int bpw) {
   constexpr int VS = pad4(J * I);
   constexpr bool kOnePass = I * I * I <= 64;       // all I weighted sums in one sweep
   constexpr int VQ = kOnePass ? pad4(I * I * I) : pad4(I * I);
   constexpr int QSTRIDE = kOnePass ? VQ : I * VQ;  // per-wave stride of the Q partials
   // keep x x^H per point in registers when it fits (it never changes)
   constexpr bool kZ = (I <= 4) && (NPT * (3 * I + J + I * I) <= 224);
-  const int f = blockIdx.x;
-  const int T = blockDim.x, nw = T / kWave;
-  const int c = (int)(threadIdx.x % I);            // the column of eq. 23 this lane solves
+  // A workgroup of W waves owns nb = min(bpw, bins left) bins with W / nb
+  // waves each (bpw in {1, 2}); the waves of one bin are consecutive.
+  const int W = blockDim.x / kWave;
+  const int f0 = blockIdx.x * bpw;
+  const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
+  const int nw = W / nb;                                   // waves per bin
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int bin = wave / nw, wl = wave % nw;               // bin in the workgroup, wave in the bin
+  const int f = f0 + bin;
+  const int T = nw * kWave;                                // lanes per bin
+  const int tb = wl * kWave + (int)(threadIdx.x & (kWave - 1));  // lane index within the bin
+  const int c = tb % I;                                    // the column of eq. 23 this lane solves
   // first frame of this wave's slot 0; a slot k is skipped by the whole wave
   // when wbase + k T >= N (a scalar branch)
-  const int wbase = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) * kWave;
-  __shared__ float sPr[I][I], sPi[I][I];
-  __shared__ float sLam[J * I];
+  const int wbase = wl * kWave;
+  __shared__ float sPr[2][I][I], sPi[2][I][I];
+  __shared__ float sLam[2][J * I];
   __shared__ float redS[kResMaxWaves * VS];
   __shared__ float redQ[kResMaxWaves * QSTRIDE];
+  const float* binS = redS + bin * nw * VS;                // this bin's wave partials
+  const float* binQ = redQ + bin * nw * QSTRIDE;
 
-  for (int t = threadIdx.x; t < I * I; t += T) {
+  for (int t = tb; t < I * I; t += T) {
     const float2 p = s.P[(size_t)f * I * I + t];
-    sPr[t / I][t % I] = p.x; sPi[t / I][t % I] = p.y;
+    sPr[bin][t / I][t % I] = p.x; sPi[bin][t / I][t % I] = p.y;
   }
-  for (int t = threadIdx.x; t < J * I; t += T) sLam[t] = s.lam[(size_t)f * J * I + t];
+  for (int t = tb; t < J * I; t += T) sLam[bin][t] = s.lam[(size_t)f * J * I + t];
 
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   float* vf = s.vs + (size_t)f * J * s.Npad;
@@ -61,7 +72,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
   float z[kZ ? NPT : 1][kZ ? I * I : 1];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    const int n = threadIdx.x + k * T;
+    const int n = tb + k * T;
     const bool ok = n < s.N;
 #pragma unroll
     for (int i = 0; i < I; ++i) {
@@ -85,11 +96,11 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 #pragma unroll
     for (int a = 0; a < I; ++a)
 #pragma unroll
-      for (int b = 0; b < I; ++b) { Pr[a][b] = sPr[a][b]; Pi[a][b] = sPi[a][b]; }
+      for (int b = 0; b < I; ++b) { Pr[a][b] = sPr[bin][a][b]; Pi[a][b] = sPi[bin][a][b]; }
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-      for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+      for (int i = 0; i < I; ++i) lam[j][i] = sLam[bin][j * I + i];
 
     // ---- phase A: E-step statistics, v update, eq. 20 summands ------------
     {
@@ -106,7 +117,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (wbase + k * T < s.N) {  // wave-uniform: skip slots no lane of the wave owns
-          const bool ok = threadIdx.x + k * T < s.N;
+          const bool ok = tb + k * T < s.N;
           float y2[I];
           as_transform_pow<I>(Pr, Pi, xr[k], xi[k], y2);
           as_point_em<I, J>(y2, lam, ilamI, v[k], S, ok);
@@ -117,13 +128,13 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
       for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int i = 0; i < I; ++i) flat[j * I + i] = S[j][i];
-      wave_totals_to_lds<J * I>(flat, redS, VS);
+      wave_totals_to_lds<J * I>(flat, redS, VS);  // slot of wave `wave`
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-      for (int i = 0; i < I; ++i) lam[j][i] = sum_waves(redS, VS, j * I + i, nw) * invN;  // eq. 20
+      for (int i = 0; i < I; ++i) lam[j][i] = sum_waves(binS, VS, j * I + i, nw) * invN;  // eq. 20
 
     // ---- phase B: weighted covariances of eq. 23 --------------------------
     if constexpr (kOnePass) {
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (wbase + k * T < s.N) {
-          const bool ok = threadIdx.x + k * T < s.N;
+          const bool ok = tb + k * T < s.N;
           float w[I];
           as_point_weights<I, J>(lam, v[k], w);
 #pragma unroll
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
       float w[NPT][I];
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        const bool ok = threadIdx.x + k * T < s.N;
+        const bool ok = tb + k * T < s.N;
         float wk[I];
         as_point_weights<I, J>(lam, v[k], wk);
 #pragma unroll
@@ -180,15 +191,15 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
     __syncthreads();
 
     // ---- per-bin solve: lane c < I computes column c of eq. 23 ------------
-    if (threadIdx.x == 0) {
+    if (tb == 0) {
 #pragma unroll
-      for (int q = 0; q < J * I; ++q) sLam[q] = lam[q / I][q % I];
+      for (int q = 0; q < J * I; ++q) sLam[bin][q] = lam[q / I][q % I];
     }
-    // Wave 0 solves (lane c: column c); the other waves go straight to the
-    // barrier that publishes the new P.
-    if (wbase == 0) {
+    // The bin's first wave solves (lane c: column c); the other waves go
+    // straight to the barrier that publishes the new P.
+    if (wl == 0) {
       float Qr[I][I], Qi[I][I];
-      const float* Qc = redQ + (kOnePass ? c * I * I : c * VQ);
+      const float* Qc = binQ + (kOnePass ? c * I * I : c * VQ);
 #pragma unroll
       for (int a = 0; a < I; ++a)
 #pragma unroll
@@ -215,9 +226,9 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
         pinvh_column<I>(P2r, P2i, c, br, bi);
         herm_solve<I>(Qr, Qi, br, bi);
       }
-      if (threadIdx.x < I) {
+      if (tb < I) {
 #pragma unroll
-        for (int a = 0; a < I; ++a) { sPr[a][c] = br[a]; sPi[a][c] = bi[a]; }
+        for (int a = 0; a < I; ++a) { sPr[bin][a][c] = br[a]; sPi[bin][a][c] = bi[a]; }
       }
     }
     __syncthreads();
@@ -226,15 +237,15 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
   // ---- write the state back ------------------------------------------------
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    const int n = threadIdx.x + k * T;
+    const int n = tb + k * T;
     if (n < s.N) {
 #pragma unroll
       for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[k][j];
     }
   }
-  for (int t = threadIdx.x; t < I * I; t += T)
-    s.P[(size_t)f * I * I + t] = make_float2(sPr[t / I][t % I], sPi[t / I][t % I]);
-  for (int t = threadIdx.x; t < J * I; t += T) s.lam[(size_t)f * J * I + t] = sLam[t];
+  for (int t = tb; t < I * I; t += T)
+    s.P[(size_t)f * I * I + t] = make_float2(sPr[bin][t / I][t % I], sPi[bin][t / I][t % I]);
+  for (int t = tb; t < J * I; t += T) s.lam[(size_t)f * J * I + t] = sLam[bin][t];
 }
 
 // Frequency-resident conventional FCA EM (Section 3.3), the same execution
@@ -367,25 +378,27 @@ constexpr int res_max_npt() {
 }
 
 template <int I, int J>
-int as_resident_fits(int N, int waves) {
+int as_resident_fits(int N, int waves, int bpw) {
   if (waves < 1 || waves > kResMaxWaves) return 0;
-  return N <= res_max_npt<I, J>() * waves * kWave ? 1 : 0;
+  if (bpw != 1 && bpw != 2) return 0;
+  if (bpw == 2 && waves < 2) return 0;
+  return N <= res_max_npt<I, J>() * (waves / bpw) * kWave ? 1 : 0;
 }
 
 template <int I, int J>
-hipError_t launch_as_iter_resident(const DevState& s, hipStream_t st, int n_iter, int waves) {
-  const int T = waves * kWave;
+hipError_t launch_as_iter_resident(const DevState& s, hipStream_t st, int n_iter, int waves, int bpw) {
+  const int T = (waves / bpw) * kWave;  // lanes per bin when the workgroup is full
   const int need = (s.N + T - 1) / T;
   constexpr int mx = res_max_npt<I, J>();
-  dim3 grid(s.F), block(T);
+  dim3 grid((s.F + bpw - 1) / bpw), block(waves * kWave);
   if (need <= 4)
-    hipLaunchKernelGGL((k_as_resident<I, J, 4>), grid, block, 0, st, s, n_iter);
+    hipLaunchKernelGGL((k_as_resident<I, J, 4>), grid, block, 0, st, s, n_iter, bpw);
   else if (need <= 8 && mx >= 8)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, s, n_iter);
+    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, s, n_iter, bpw);
   else if (need <= 12 && mx >= 12)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, s, n_iter);
+    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, s, n_iter, bpw);
   else if (need <= 16 && mx >= 16)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, s, n_iter);
+    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, s, n_iter, bpw);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

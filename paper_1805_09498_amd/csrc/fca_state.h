@@ -41,8 +41,8 @@ struct DevState {
 // Host launchers of one (I, J) instantiation.
 struct KernelSet {
   hipError_t (*as_iter_stream)(const DevState&, hipStream_t);
-  hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
-  int (*as_resident_fits)(int N, int waves);
+  hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves, int bpw);
+  int (*as_resident_fits)(int N, int waves, int bpw);
   hipError_t (*em_iter)(const DevState&, hipStream_t);
   hipError_t (*em_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
   int (*em_resident_fits)(int N, int waves);

@@ -4,7 +4,8 @@ step of FCA / FastFCA-AS runs in the library's HIP kernels.
 The functions carry the names of the C ABI (include/fastfca.h):
 ``fca_init``, ``fastfca_as_iterate``, ``fca_em_iterate``,
 ``fca_wiener_separate``, ``fca_loglik``, ``fca_get_params``,
-``fca_set_params``, ``fca_set_option``, ``fca_last_error``, ``fca_destroy``.
+``fca_set_params``, ``fca_set_option``, ``fca_get_option``, ``fca_last_error``,
+``fca_destroy``.
 Arrays are torch tensors on the GPU in the ABI layouts (complex64 /
 float32, C-contiguous); PyTorch provides the device memory and the stream.
 
@@ -32,7 +33,7 @@ FCA_METHOD_EM = 1
 
 EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
             "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
-            "fca_last_error", "fca_destroy")
+            "fca_get_option", "fca_last_error", "fca_destroy")
 
 
 def _load():
@@ -56,6 +57,8 @@ def _load():
     lib.fca_set_params.restype = i
     lib.fca_set_option.argtypes = [vp, c, ctypes.c_longlong]
     lib.fca_set_option.restype = i
+    lib.fca_get_option.argtypes = [vp, c, ctypes.POINTER(ctypes.c_longlong)]
+    lib.fca_get_option.restype = i
     lib.fca_last_error.argtypes = [vp]
     lib.fca_last_error.restype = c
     lib.fca_destroy.argtypes = [vp]
@@ -184,11 +187,17 @@ def fca_set_params(ctx, v=None, lam=None, P_or_R=None):
     _check(lib.fca_set_params(ctx.handle, _ptr(v, torch.float32, (F, N, J), "v"),
                               _ptr(lam, torch.float32, (F, J, I), "lam"),
                               _ptr(P_or_R, torch.complex64, mshape, "P_or_R")), ctx)
-    ctx._keep = ctx._keep + (v, lam, P_or_R)
+    ctx._keep_set = (v, lam, P_or_R)   # referenced until the next call
 
 
 def fca_set_option(ctx, key, value):
     _check(lib.fca_set_option(ctx.handle, key.encode(), int(value)), ctx)
+
+
+def fca_get_option(ctx, key):
+    out = ctypes.c_longlong()
+    _check(lib.fca_get_option(ctx.handle, key.encode(), ctypes.byref(out)), ctx)
+    return out.value
 
 
 def fca_destroy(ctx):

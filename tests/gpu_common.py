@@ -40,11 +40,12 @@ def to_dev(p, R0=None):
     return t
 
 
-def run_as(ff, p, n_iter, path=0, waves=0, K=1):
+def run_as(ff, p, n_iter, path=0, waves=0, K=1, bpw=0):
     t = to_dev(p)
     ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
     ff.fca_set_option(ctx, "path", path)
     ff.fca_set_option(ctx, "waves", waves)
+    ff.fca_set_option(ctx, "bins_per_wg", bpw)
     ff.fca_set_option(ctx, "K", K)
     ff.fastfca_as_iterate(ctx, n_iter)
     return ctx

@@ -45,7 +45,7 @@ def test_header_declares_the_expected_calls():
     assert declared_functions() == sorted([
         "fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
         "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
-        "fca_last_error", "fca_destroy"])
+        "fca_get_option", "fca_last_error", "fca_destroy"])
 
 
 def test_every_declared_function_is_exported(lib):

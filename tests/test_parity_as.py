@@ -56,10 +56,10 @@ def test_loglik_at_initial_point(ff):
     assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
 
 
-@pytest.mark.parametrize("waves", [1, 2, 4])
-def test_resident_wave_counts_agree(ff, waves):
-    p = problem(**SPEECH)
-    ctx = run_as(ff, p, 1, path=1, waves=waves)
+@pytest.mark.parametrize("waves,bpw", [(1, 1), (2, 1), (4, 1), (2, 2), (4, 2)])
+def test_resident_launch_shapes_agree(ff, waves, bpw):
+    p = problem(**SPEECH)          # F = 513: the last workgroup of a 2-bin shape holds one bin
+    ctx = run_as(ff, p, 1, path=1, waves=waves, bpw=bpw)
     v, lam, P = params(ff, ctx)
     v_ref, lam_ref, P_ref = oracle_as(p, 1)
     assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM

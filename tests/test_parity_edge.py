@@ -72,7 +72,7 @@ def test_method_mismatch_and_options(ff):
     with pytest.raises(ff.FcaError) as e:
         ff.fca_em_iterate(ctx, 1)
     assert e.value.status == ff.FCA_ERR_STATE
-    for key, val in [("K", 0), ("K", 65), ("path", 3), ("waves", 3), ("nope", 1)]:
+    for key, val in [("K", 0), ("K", 65), ("path", 3), ("waves", 3), ("bins_per_wg", 3), ("autotune", 2), ("nope", 1)]:
         with pytest.raises(ff.FcaError) as e:
             ff.fca_set_option(ctx, key, val)
         assert e.value.status == ff.FCA_ERR_ARG
