@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="speech10s")
     ap.add_argument("--iters", type=int, default=None, help="override the workload's iteration count")
+    ap.add_argument("--F", type=int, default=None, help="override the number of frequency bins")
+    ap.add_argument("--N", type=int, default=None, help="override the number of frames")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--bins-per-wg", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=1)
@@ -157,8 +159,10 @@ def main():
 
     cfg = dict(synth.CONFIGS[args.config])
     iters = args.iters or cfg["iters"]
+    over = {k: getattr(args, k) for k in ("F", "N") if getattr(args, k)}
+    cfg.update(over)
     I, J, F, N = cfg["I"], cfg["J"], cfg["F"], cfg["N"]
-    prob = synth.make_config(args.config).rounded_c64()
+    prob = synth.make_config(args.config, **over).rounded_c64()
     dev = torch.device("cuda:0")
     x = torch.from_numpy(prob.x.astype(np.complex64)).to(dev)
     v0 = torch.from_numpy(prob.v0.astype(np.float32)).to(dev)
@@ -225,7 +229,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: I={I}, J={J}, F={F}, N={N}, {iters} FastFCA-AS iterations "
+        "config": {"workload": f"{args.config}{' (overridden)' if over else ''}: I={I}, J={J}, F={F}, N={N}, {iters} FastFCA-AS iterations "
                                f"+ log-likelihood + Wiener filter per step, complex64",
                    "I": I, "J": J, "F": F, "N": N, "iterations": iters, "parallelism": "1 GPU"},
     }

@@ -58,44 +58,42 @@ __device__ __forceinline__ void as_transform(const float (&Pr)[I][I], const floa
   }
 }
 
-// E-step statistics and v update of one point.
-//   r_ji = |mu~_ji|^2 + phi~_ji = g (g |y_i|^2 + e_ji),  g = v_j lambda_ji / d_i,
-//   e_ji = sum_{k != j} v_k lambda_ki  (eq. 16-17, phi~ = v lambda e / d),
-//   v_j <- (1/I) sum_i r_ji / lambda_ji                                (eq. 19)
-// and S_ji += r_ji / v_j(new) (the summand of eq. 20) when `take`.
+// E-step statistics and v update of one point, in a form with fewer
+// operations that is algebraically identical to eq. 16-17, 19 and 20:
+//   d_i = sum_j v_j lambda_ji,   g_ji = v_j lambda_ji / d_i  (diagonal Wiener gain),
+//   |mu~_ji|^2 + phi~_ji = g_ji u_ji  with  u_ji = g_ji |y_i|^2 + d_i - v_j lambda_ji
+//                                            = d_i + v_j lambda_ji (|y_i|^2 / d_i - 1),
+//   v_j <- (1/I) sum_i g_ji u_ji / lambda_ji = (v_j / I) U_j,  U_j = sum_i u_ji / d_i  (eq. 19),
+//   summand of eq. 20:  g_ji u_ji / v_j(new) = I lambda_ji (u_ji / d_i) / U_j.
+// The point adds (u_ji / d_i) / U_j to S_ji and updates v (when `take`); the
+// caller applies the factor I lambda_ji / N once per bin after summing over
+// the frames.
 template <int I, int J>
 __device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&lam)[J][I],
-                                            const float (&ilamI)[J][I], float (&v)[J],
-                                            float (&S)[J][I], bool take) {
-  float r[J][I];
+                                            float (&v)[J], float (&S)[J][I], bool take) {
+  float ut[J][I];
 #pragma unroll
   for (int i = 0; i < I; ++i) {
     float vl[J];
+    float d = 0.f;
 #pragma unroll
-    for (int j = 0; j < J; ++j) vl[j] = v[j] * lam[j][i];
-    float pre[J];
-    float acc = 0.f;
+    for (int j = 0; j < J; ++j) { vl[j] = v[j] * lam[j][i]; d += vl[j]; }
+    const float t = rcp(d);
+    const float h = fmaf(y2[i], t, -1.0f);
 #pragma unroll
-    for (int j = 0; j < J; ++j) { pre[j] = acc; acc += vl[j]; }
-    const float id = rcp(acc);
-    float suf = 0.f;
-#pragma unroll
-    for (int j = J - 1; j >= 0; --j) {
-      const float e = pre[j] + suf;
-      suf += vl[j];
-      const float g = vl[j] * id;
-      r[j][i] = g * fmaf(g, y2[i], e);
-    }
+    for (int j = 0; j < J; ++j) ut[j][i] = fmaf(vl[j], h, d) * t;
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    float vn = 0.f;
+    float U = ut[j][0];
 #pragma unroll
-    for (int i = 0; i < I; ++i) vn = fmaf(r[j][i], ilamI[j][i], vn);
-    v[j] = vn;
-    const float iv = take ? rcp(vn) : 0.f;
+    for (int i = 1; i < I; ++i) U += ut[j][i];
+    // A lane that does not own a frame (take = false) keeps its v, so that
+    // padded lanes stay finite over any number of iterations.
+    v[j] = take ? v[j] * U * (1.0f / float(I)) : v[j];
+    const float rU = take ? rcp(U) : 0.f;
 #pragma unroll
-    for (int i = 0; i < I; ++i) S[j][i] = fmaf(r[j][i], iv, S[j][i]);
+    for (int i = 0; i < I; ++i) S[j][i] = fmaf(ut[j][i], rU, S[j][i]);
   }
 }
 
@@ -176,15 +174,12 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
   for (int t = threadIdx.x; t < I * I; t += kBlock) sP[t] = s.P[(size_t)f * I * I + t];
   for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
   __syncthreads();
-  float Pr[I][I], Pi[I][I], lam[J][I], ilamI[J][I];
+  float Pr[I][I], Pi[I][I], lam[J][I];
   load_P<I>(sP, Pr, Pi);
 #pragma unroll
   for (int j = 0; j < J; ++j)
 #pragma unroll
-    for (int i = 0; i < I; ++i) {
-      lam[j][i] = sLam[j * I + i];
-      ilamI[j][i] = 1.0f / (float(I) * lam[j][i]);
-    }
+    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
   float S[J][I];
 #pragma unroll
   for (int j = 0; j < J; ++j)
@@ -204,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
       for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
       float y2[I];
       as_transform_pow<I>(Pr, Pi, xr, xi, y2);
-      as_point_em<I, J>(y2, lam, ilamI, v, S, true);
+      as_point_em<I, J>(y2, lam, v, S, true);
 #pragma unroll
       for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[j];
     }
@@ -226,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
   for (int t = threadIdx.x; t < J * I; t += kBlock) {
     float acc = 0.f;
     for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
-    sLam[t] = acc * invN;
+    sLam[t] = acc * (float(I) * s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
   }
   __syncthreads();
   float lam[J][I];
@@ -280,7 +275,8 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
     for (int j = 0; j < J; ++j) {
       float acc = 0.f;
       for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + j * I + i];
-      s.lam[(size_t)f * J * I + j * I + i] = acc * invN;
+      float* l = s.lam + (size_t)f * J * I + j * I + i;
+      *l = acc * (float(I) * (*l) * invN);  // eq. 20 (old lambda times the scaled sum)
     }
     // Q_i of eq. 23 from the tile partials.
     float A[I * I];

@@ -104,11 +104,6 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 
     // ---- phase A: E-step statistics, v update, eq. 20 summands ------------
     {
-      float ilamI[J][I];
-#pragma unroll
-      for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int i = 0; i < I; ++i) ilamI[j][i] = rcp(float(I) * lam[j][i]);
       float S[J][I];
 #pragma unroll
       for (int j = 0; j < J; ++j)
@@ -120,7 +115,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
           const bool ok = tb + k * T < s.N;
           float y2[I];
           as_transform_pow<I>(Pr, Pi, xr[k], xi[k], y2);
-          as_point_em<I, J>(y2, lam, ilamI, v[k], S, ok);
+          as_point_em<I, J>(y2, lam, v[k], S, ok);
         }
       }
       float flat[J * I];
@@ -134,7 +129,8 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-      for (int i = 0; i < I; ++i) lam[j][i] = sum_waves(binS, VS, j * I + i, nw) * invN;  // eq. 20
+      for (int i = 0; i < I; ++i)  // eq. 20: old lambda times the scaled sum
+        lam[j][i] = sum_waves(binS, VS, j * I + i, nw) * (float(I) * lam[j][i] * invN);
 
     // ---- phase B: weighted covariances of eq. 23 --------------------------
     if constexpr (kOnePass) {
@@ -146,12 +142,13 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (wbase + k * T < s.N) {
-          const bool ok = tb + k * T < s.N;
+          // lanes past N hold x = 0 and their initial v (kept by phase A), so
+          // their weight is finite and they add nothing
           float w[I];
           as_point_weights<I, J>(lam, v[k], w);
 #pragma unroll
           for (int i = 0; i < I; ++i) {
-            const float wi = ok ? w[i] : 0.f;
+            const float wi = w[i];
             if constexpr (kZ) {
 #pragma unroll
               for (int q = 0; q < I * I; ++q) A[i][q] = fmaf(wi, z[k][q], A[i][q]);
@@ -170,13 +167,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
     } else {
       float w[NPT][I];
 #pragma unroll
-      for (int k = 0; k < NPT; ++k) {
-        const bool ok = tb + k * T < s.N;
-        float wk[I];
-        as_point_weights<I, J>(lam, v[k], wk);
-#pragma unroll
-        for (int i = 0; i < I; ++i) w[k][i] = ok ? wk[i] : 0.f;
-      }
+      for (int k = 0; k < NPT; ++k) as_point_weights<I, J>(lam, v[k], w[k]);  // x = 0, v kept past N
 #pragma unroll
       for (int i = 0; i < I; ++i) {
         float A[I * I];

@@ -66,6 +66,22 @@ def test_loglik_and_wiener_edge(ff, I, J, F, N):
     assert rel(s, oracle.wiener_as(p.x, v, lam, P)) <= TOL_PARAM
 
 
+@pytest.mark.parametrize("J", [1, 2, 3])
+def test_long_run_ragged_frames_stay_finite(ff, J):
+    """Lanes past N (padding) must stay finite over long in-kernel runs: 300
+    iterations in one call, N not a multiple of the lane count, all shapes.
+    Compared with the oracle on the log-likelihood after the run."""
+    p = problem(2, J, 5, 70, seed=31 + J)
+    v, lam, P = oracle_as(p, 300)
+    L_ref = oracle.loglik_as(p.x, v, lam, P)
+    for waves, bpw in ((1, 1), (2, 1), (4, 1), (4, 2)):
+        ctx = run_as(ff, p, 300, path=1, waves=waves, bpw=bpw)
+        vg, lg, Pg = params(ff, ctx)
+        assert np.isfinite(vg).all() and np.isfinite(lg).all() and np.isfinite(Pg).all()
+        L = ff.fca_loglik(ctx)
+        assert abs(L - L_ref) <= 1e-3 * abs(L_ref), (waves, bpw, L, L_ref)
+
+
 def test_method_mismatch_and_options(ff):
     p = problem(3, 3, 4, 20, seed=1)
     ctx = run_as(ff, p, 0)
