@@ -125,14 +125,19 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * "check_finite" (0/1: after each iterate call, synchronise and return
  * FCA_ERR_NONFINITE if a parameter is NaN/Inf), "path" (0 = automatic,
  * 1 = force the frequency-resident kernels, 2 = force the streaming
- * kernels), "waves" (64-lane waves per workgroup of the frequency-resident
+ * kernels; K > 1 at I > 4 always uses the streaming kernels), "waves"
+ * (64-lane waves per workgroup of the frequency-resident
  * kernels: 0 = automatic, 1, 2 or 4), "bins_per_wg" (frequency bins per
  * workgroup of the frequency-resident FastFCA-AS kernel: 0 = automatic, 1 or
  * 2; 2 needs at least 2 waves), "autotune" (1 = default: unless a shape is
  * forced by the options above, the first iterate call of a context times
  * every launch shape that fits on a saved copy of the state, restores it and
- * caches the fastest for the process under (method, I, J, F, N); this call
- * synchronises the stream.  0 = fixed preference order).  Unknown keys or
+ * caches the fastest for the process under (method, I, J, F, N, K); this call
+ * synchronises the stream.  0 = fixed preference order).  When the
+ * environment variable FASTFCA_TUNE_CACHE names a writable file, measured
+ * shapes are also appended to it and read back by later processes (keyed by
+ * GPU architecture, compute-unit count and library build; unreadable or
+ * unwritable files only cost a re-measurement).  Unknown keys or
  * values out of range give FCA_ERR_ARG; a forced shape that cannot hold N
  * frames per bin makes the iterate call return FCA_ERR_ARG.  Results are
  * bitwise reproducible for a given launch shape. */
@@ -152,6 +157,52 @@ const char *fca_last_error(const fca_ctx *ctx);
 /* Release all device memory of the context (after synchronising its stream).
  * NULL is ignored. */
 void fca_destroy(fca_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batched FastFCA-AS: many mixtures of different (F, N, I, J) advanced
+ * together.  Each mixture is an ordinary FCA_METHOD_AS context owned by the
+ * batch; mixtures of equal (I, J) advance in one launch per batch step over a
+ * table of (mixture, bin) tiles ordered by decreasing N.  One batch step is
+ * recorded once per iteration count as a HIP graph and replayed (when the
+ * stream is not NULL and the "graph" option is on).
+ * ------------------------------------------------------------------------ */
+typedef struct fca_batch fca_batch;
+
+/* n_mix mixtures; F, N, I, J are HOST arrays of n_mix sizes; x, v0, lam0, P0
+ * are HOST arrays of n_mix DEVICE pointers in the layouts of fca_init.  The
+ * same checks as fca_init apply per mixture (error message names it).  The
+ * caller may free the inputs once the stream has passed this call. */
+fca_status fca_batch_init(fca_batch **out, int n_mix, const int *F, const int *N, const int *I,
+                          const int *J, const fca_c64 *const *x, const float *const *v0,
+                          const float *const *lam0, const fca_c64 *const *P0, void *hip_stream);
+
+/* n_iter hybrid iterations of every mixture (Section 4.4).  The first call
+ * times the candidate launch shapes per (I, J) group (synchronising the
+ * stream; the state is restored; FASTFCA_TUNE_CACHE as for fca_set_option's
+ * "autotune").  Asynchronous otherwise. */
+fca_status fca_batch_iterate(fca_batch *b, int n_iter);
+
+/* The context of mixture m (owned by the batch: do not destroy it) for
+ * fca_loglik, fca_wiener_separate, fca_get_params, fca_set_params. */
+fca_status fca_batch_context(fca_batch *b, int m, fca_ctx **ctx);
+
+/* "graph" (1 = default: replay a recorded HIP graph per batch step; 0 =
+ * launch directly), "autotune" (1 = default, 0 = smallest fitting shape),
+ * "waves" (0 = automatic, 1, 2 or 4), "K" (fixed-point steps, 1..64, applied
+ * to every mixture). */
+fca_status fca_batch_set_option(fca_batch *b, const char *key, long long value);
+
+/* "groups" (number of (I, J) groups; group ignored), per group index:
+ * "group_I", "group_J", "group_tiles", "group_waves" (waves per workgroup
+ * chosen, 0 = streaming kernels, -1 = not tuned yet).  value: host pointer. */
+fca_status fca_batch_get_option(fca_batch *b, const char *key, int group, long long *value);
+
+/* Message for the last error on b, or for the calling thread's last failed
+ * fca_batch_init when b is NULL.  Never NULL. */
+const char *fca_batch_last_error(const fca_batch *b);
+
+/* Synchronise the stream and release the batch and its contexts. */
+void fca_batch_destroy(fca_batch *b);
 
 #ifdef __cplusplus
 }

@@ -34,25 +34,10 @@ const KernelSet* kernel_set(int I, int J) {
 }
 }  // namespace fca
 
+#include "fca_internal.h"
+
 using fca::DevState;
 using fca::KernelSet;
-
-struct fca_ctx {
-  fca_method method;
-  int F, N, I, J;
-  hipStream_t stream;
-  const KernelSet* ks;
-  DevState s;
-  void* arena;
-  int check_finite;
-  int path;   // 0 auto, 1 resident, 2 streaming
-  int waves;  // 0 auto
-  int bpw;    // bins per workgroup of the resident AS kernel, 0 auto
-  int autotune;  // 1: time the candidate launch shapes once per (method, I, J, F, N)
-  float* backup;  // state copy used while tuning: vs, lam, P (AS) or vs, R (EM)
-  int last_waves, last_bpw;  // launch shape of the last iterate call (waves 0: streaming)
-  std::string err;
-};
 
 namespace {
 
@@ -98,10 +83,11 @@ struct Shape {
 };
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, Shape> g_tuned;
+std::map<std::tuple<int, int, int, int, int, int>, Shape> g_tuned;  // (method, I, J, F, N, K)
 
 bool shape_fits(const fca_ctx* c, Shape sh) {
   if (sh.waves == 0) return true;
+  if (c->method == FCA_METHOD_AS && c->s.K > 1 && c->I > fca::kResMaxIK) return false;
   return c->method == FCA_METHOD_AS ? c->ks->as_resident_fits(c->N, sh.waves, sh.bpw) != 0
                                     : (sh.bpw == 1 && c->ks->em_resident_fits(c->N, sh.waves) != 0);
 }
@@ -163,6 +149,11 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
   const int ncand = as ? 6 : 4;
   // Forced choices first.
   if (c->path == 2) { *out = Shape{0, 0}; return FCA_OK; }
+  if (c->path == 1) {
+    bool any = false;
+    for (int k = 0; k < ncand; ++k) any = any || (cands[k].waves > 0 && shape_fits(c, cands[k]));
+    if (!any) return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this problem (N, or K > 1 at I > 4)");
+  }
   const bool forced = c->waves > 0 || c->bpw > 0;
   if (forced || !c->autotune) {
     for (int k = 0; k < ncand; ++k) {
@@ -177,11 +168,27 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
     *out = Shape{0, 0};
     return FCA_OK;
   }
-  const auto key = std::make_tuple((int)c->method, c->I, c->J, c->F, c->N);
+  const auto key = std::make_tuple((int)c->method, c->I, c->J, c->F, c->N, c->s.K);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
-    if (it != g_tuned.end() && (c->path == 0 || it->second.waves > 0)) { *out = it->second; return FCA_OK; }
+    if (it != g_tuned.end() && (c->path == 0 || it->second.waves > 0) && shape_fits(c, it->second)) {
+      *out = it->second;
+      return FCA_OK;
+    }
+  }
+  const std::string disk_key = fca::tune_key_prefix() + (c->method == FCA_METHOD_AS ? " as" : " em") +
+                               " I=" + std::to_string(c->I) + " J=" + std::to_string(c->J) +
+                               " F=" + std::to_string(c->F) + " N=" + std::to_string(c->N) +
+                               " K=" + std::to_string(c->s.K);
+  {
+    Shape sh{0, 0};
+    if (c->path == 0 && fca::tune_cache_get(disk_key, &sh.waves, &sh.bpw) && shape_fits(c, sh)) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[key] = sh;
+      *out = sh;
+      return FCA_OK;
+    }
   }
   // Tune: for each fitting shape, the marginal cost per iteration
   // (T(n1 + n2) - T(n1)) / n2 (best of two trials each, from the saved state)
@@ -222,9 +229,12 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(c, e, "tuner run");
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (c->path == 0) g_tuned[key] = best_sh;
+  if (c->path == 0) {
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[key] = best_sh;
+    }
+    fca::tune_cache_put(disk_key, best_sh.waves, best_sh.bpw);
   }
   *out = best_sh;
   return FCA_OK;
@@ -255,6 +265,27 @@ fca_status post_check(fca_ctx* c) {
 
 }  // namespace
 
+namespace fca {
+hipError_t copy_state(fca_ctx* c, bool save) { return ::copy_state(c, save); }
+
+fca_status validate_init(fca_method method, int F, int N, int I, int J, const void* x, const void* v0,
+                         const void* lam0, const void* P0, const void* R0, std::string* msg) {
+  auto bad = [&](fca_status st, const char* m) { *msg = m; return st; };
+  if (method != FCA_METHOD_AS && method != FCA_METHOD_EM) return bad(FCA_ERR_ARG, "unknown method");
+  if (F < 1 || N < 1 || I < 1 || J < 1) return bad(FCA_ERR_ARG, "F, N, I, J must be positive");
+  if (I > 8 || J > 9) return bad(FCA_ERR_UNSUPPORTED, "supported sizes are 1 <= I <= 8, 1 <= J <= 9");
+  if (N < I) return bad(FCA_ERR_ARG, "N must be at least I (the weighted covariances are singular otherwise)");
+  const long long Npad = ((long long)N + 63) / 64 * 64;
+  const int mx = I > J ? I : J;
+  if ((long long)F * Npad * 2 * mx >= (1LL << 31)) return bad(FCA_ERR_ARG, "problem too large (N*F*max(I,J) >= 2^31)");
+  if (!x || !v0 || !lam0 || !P0) return bad(FCA_ERR_ARG, "x, v0, lam0 and P0 must be non-NULL device pointers");
+  if (!aligned(x, 8) || !aligned(P0, 8) || !aligned(v0, 4) || !aligned(lam0, 4) || (R0 && !aligned(R0, 8)))
+    return bad(FCA_ERR_ARG, "misaligned pointer (complex arrays need 8-byte, float arrays 4-byte alignment)");
+  if (method == FCA_METHOD_AS && R0) return bad(FCA_ERR_ARG, "R0 must be NULL for FCA_METHOD_AS");
+  return FCA_OK;
+}
+}  // namespace fca
+
 extern "C" {
 
 fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J, const fca_c64* x,
@@ -262,17 +293,12 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
                     void* hip_stream) {
   if (!out) return fail(nullptr, FCA_ERR_ARG, "out is NULL");
   *out = nullptr;
-  if (method != FCA_METHOD_AS && method != FCA_METHOD_EM) return fail(nullptr, FCA_ERR_ARG, "unknown method");
-  if (F < 1 || N < 1 || I < 1 || J < 1) return fail(nullptr, FCA_ERR_ARG, "F, N, I, J must be positive");
-  if (I > 8 || J > 9) return fail(nullptr, FCA_ERR_UNSUPPORTED, "supported sizes are 1 <= I <= 8, 1 <= J <= 9");
-  if (N < I) return fail(nullptr, FCA_ERR_ARG, "N must be at least I (the weighted covariances are singular otherwise)");
+  {
+    std::string msg;
+    const fca_status st = fca::validate_init(method, F, N, I, J, x, v0, lam0, P0, R0, &msg);
+    if (st != FCA_OK) return fail(nullptr, st, msg);
+  }
   const long long Npad = ((long long)N + 63) / 64 * 64;
-  const int mx = I > J ? I : J;
-  if ((long long)F * Npad * 2 * mx >= (1LL << 31)) return fail(nullptr, FCA_ERR_ARG, "problem too large (N*F*max(I,J) >= 2^31)");
-  if (!x || !v0 || !lam0 || !P0) return fail(nullptr, FCA_ERR_ARG, "x, v0, lam0 and P0 must be non-NULL device pointers");
-  if (!aligned(x, 8) || !aligned(P0, 8) || !aligned(v0, 4) || !aligned(lam0, 4) || (R0 && !aligned(R0, 8)))
-    return fail(nullptr, FCA_ERR_ARG, "misaligned pointer (complex arrays need 8-byte, float arrays 4-byte alignment)");
-  if (method == FCA_METHOD_AS && R0) return fail(nullptr, FCA_ERR_ARG, "R0 must be NULL for FCA_METHOD_AS");
   const KernelSet* ks = fca::kernel_set(I, J);
   if (!ks) return fail(nullptr, FCA_ERR_UNSUPPORTED, "(I, J) not instantiated");
 

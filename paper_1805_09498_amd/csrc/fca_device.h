@@ -98,66 +98,21 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// ---------------------------------------------------------------------------
-// Small dense complex linear algebra, one matrix per lane.
-// ---------------------------------------------------------------------------
-
-// Solve M z = rhs for one right-hand side by Gaussian elimination with
-// partial pivoting (the pivot of column k is the largest-modulus entry at or
-// below the diagonal).  M and rhs are destroyed.  Returns false when a pivot
-// is exactly zero.
-template <int I>
-__device__ inline bool lu_solve(float (&Mr)[I][I], float (&Mi)[I][I], float (&br)[I], float (&bi)[I]) {
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < I; ++k) {
-#pragma unroll
-    for (int r = k + 1; r < I; ++r) {
-      const float cur = Mr[k][k] * Mr[k][k] + Mi[k][k] * Mi[k][k];
-      const float cand = Mr[r][k] * Mr[r][k] + Mi[r][k] * Mi[r][k];
-      if (cand > cur) {
-#pragma unroll
-        for (int c = 0; c < I; ++c) {
-          float t = Mr[k][c]; Mr[k][c] = Mr[r][c]; Mr[r][c] = t;
-          t = Mi[k][c]; Mi[k][c] = Mi[r][c]; Mi[r][c] = t;
-        }
-        float t = br[k]; br[k] = br[r]; br[r] = t;
-        t = bi[k]; bi[k] = bi[r]; bi[r] = t;
-      }
-    }
-    const float pr = Mr[k][k], pi = Mi[k][k];
-    const float den = pr * pr + pi * pi;
-    ok = ok && (den > 0.0f);
-    const float inv = rcp(den);
-    const float qr = pr * inv, qi = -pi * inv;  // 1 / pivot
-#pragma unroll
-    for (int r = k + 1; r < I; ++r) {
-      const float lr = Mr[r][k] * qr - Mi[r][k] * qi;
-      const float li = Mr[r][k] * qi + Mi[r][k] * qr;
-#pragma unroll
-      for (int c = k + 1; c < I; ++c) {
-        Mr[r][c] -= lr * Mr[k][c] - li * Mi[k][c];
-        Mi[r][c] -= lr * Mi[k][c] + li * Mr[k][c];
-      }
-      br[r] -= lr * br[k] - li * bi[k];
-      bi[r] -= lr * bi[k] + li * br[k];
-    }
-  }
-#pragma unroll
-  for (int k = I - 1; k >= 0; --k) {
-    float sr = br[k], si = bi[k];
-#pragma unroll
-    for (int c = k + 1; c < I; ++c) {
-      sr -= Mr[k][c] * br[c] - Mi[k][c] * bi[c];
-      si -= Mr[k][c] * bi[c] + Mi[k][c] * br[c];
-    }
-    const float pr = Mr[k][k], pi = Mi[k][k];
-    const float inv = rcp(pr * pr + pi * pi);
-    br[k] = (sr * pr + si * pi) * inv;
-    bi[k] = (si * pr - sr * pi) * inv;
-  }
-  return ok;
+// Scalar helpers of the per-bin solvers, which run in float or double.
+template <typename T>
+__device__ __forceinline__ T rcpT(T x);
+template <>
+__device__ __forceinline__ float rcpT<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+// Hardware estimate refined by two Newton steps r <- r + r (1 - x r) (each
+// squares the relative error), instead of the longer IEEE division sequence.
+template <>
+__device__ __forceinline__ double rcpT<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
+__device__ __forceinline__ float sqrtT(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrtT(double x) { return __builtin_sqrt(x); }
 
 // ln|det M| by the same elimination (M destroyed).
 template <int I>
@@ -196,27 +151,88 @@ __device__ inline float lu_logabsdet(float (&Mr)[I][I], float (&Mi)[I][I]) {
   return acc;
 }
 
+// ---------------------------------------------------------------------------
+// Small dense complex linear algebra, one matrix per lane.
+// ---------------------------------------------------------------------------
+
+// Solve M z = rhs for one right-hand side by Gaussian elimination with
+// partial pivoting (the pivot of column k is the largest-modulus entry at or
+// below the diagonal).  M and rhs are destroyed.  Returns false when a pivot
+// is exactly zero.
+template <int I, typename T = float>
+__device__ inline bool lu_solve(T (&Mr)[I][I], T (&Mi)[I][I], T (&br)[I], T (&bi)[I]) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < I; ++k) {
+#pragma unroll
+    for (int r = k + 1; r < I; ++r) {
+      const T cur = Mr[k][k] * Mr[k][k] + Mi[k][k] * Mi[k][k];
+      const T cand = Mr[r][k] * Mr[r][k] + Mi[r][k] * Mi[r][k];
+      if (cand > cur) {
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+          T t = Mr[k][c]; Mr[k][c] = Mr[r][c]; Mr[r][c] = t;
+          t = Mi[k][c]; Mi[k][c] = Mi[r][c]; Mi[r][c] = t;
+        }
+        T t = br[k]; br[k] = br[r]; br[r] = t;
+        t = bi[k]; bi[k] = bi[r]; bi[r] = t;
+      }
+    }
+    const T pr = Mr[k][k], pi = Mi[k][k];
+    const T den = pr * pr + pi * pi;
+    ok = ok && (den > T(0));
+    const T inv = rcpT(den);
+    const T qr = pr * inv, qi = -pi * inv;  // 1 / pivot
+#pragma unroll
+    for (int r = k + 1; r < I; ++r) {
+      const T lr = Mr[r][k] * qr - Mi[r][k] * qi;
+      const T li = Mr[r][k] * qi + Mi[r][k] * qr;
+#pragma unroll
+      for (int c = k + 1; c < I; ++c) {
+        Mr[r][c] -= lr * Mr[k][c] - li * Mi[k][c];
+        Mi[r][c] -= lr * Mi[k][c] + li * Mr[k][c];
+      }
+      br[r] -= lr * br[k] - li * bi[k];
+      bi[r] -= lr * bi[k] + li * br[k];
+    }
+  }
+#pragma unroll
+  for (int k = I - 1; k >= 0; --k) {
+    T sr = br[k], si = bi[k];
+#pragma unroll
+    for (int c = k + 1; c < I; ++c) {
+      sr -= Mr[k][c] * br[c] - Mi[k][c] * bi[c];
+      si -= Mr[k][c] * bi[c] + Mi[k][c] * br[c];
+    }
+    const T pr = Mr[k][k], pi = Mi[k][k];
+    const T inv = rcpT(pr * pr + pi * pi);
+    br[k] = (sr * pr + si * pi) * inv;
+    bi[k] = (si * pr - sr * pi) * inv;
+  }
+  return ok;
+}
+
 // Cholesky factor of a Hermitian positive-definite matrix given by its upper
 // triangle: A = L L^H with L lower triangular and real positive diagonal.
 // On return Lr/Li hold L (strictly-upper part unused) and dinv the
 // reciprocal diagonal.  Returns false if A is not numerically PD.
-template <int I>
-__device__ inline bool cholesky(const float (&Ar)[I][I], const float (&Ai)[I][I],
-                                float (&Lr)[I][I], float (&Li)[I][I], float (&dinv)[I]) {
+template <int I, typename T = float>
+__device__ inline bool cholesky(const T (&Ar)[I][I], const T (&Ai)[I][I],
+                                T (&Lr)[I][I], T (&Li)[I][I], T (&dinv)[I]) {
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < I; ++k) {
-    float s = Ar[k][k];
+    T s = Ar[k][k];
 #pragma unroll
     for (int m = 0; m < k; ++m) s -= Lr[k][m] * Lr[k][m] + Li[k][m] * Li[k][m];
-    ok = ok && (s > 0.0f);
-    const float dk = __builtin_sqrtf(fmaxf(s, 1e-37f));
-    const float ik = rcp(dk);
-    Lr[k][k] = dk; Li[k][k] = 0.0f; dinv[k] = ik;
+    ok = ok && (s > T(0));
+    const T dk = sqrtT(s > T(1e-37) ? s : T(1e-37));
+    const T ik = rcpT(dk);
+    Lr[k][k] = dk; Li[k][k] = T(0); dinv[k] = ik;
 #pragma unroll
     for (int r = k + 1; r < I; ++r) {
       // A[r][k] = conj(A[k][r]);  L[r][k] = (A[r][k] - sum_m L[r][m] conj(L[k][m])) / L[k][k]
-      float sr = Ar[k][r], si = -Ai[k][r];
+      T sr = Ar[k][r], si = -Ai[k][r];
 #pragma unroll
       for (int m = 0; m < k; ++m) {
         sr -= Lr[r][m] * Lr[k][m] + Li[r][m] * Li[k][m];
@@ -229,12 +245,12 @@ __device__ inline bool cholesky(const float (&Ar)[I][I], const float (&Ai)[I][I]
 }
 
 // Solve (L L^H) z = b in place.
-template <int I>
-__device__ inline void cholesky_solve(const float (&Lr)[I][I], const float (&Li)[I][I],
-                                      const float (&dinv)[I], float (&br)[I], float (&bi)[I]) {
+template <int I, typename T = float>
+__device__ inline void cholesky_solve(const T (&Lr)[I][I], const T (&Li)[I][I],
+                                      const T (&dinv)[I], T (&br)[I], T (&bi)[I]) {
 #pragma unroll
   for (int k = 0; k < I; ++k) {
-    float sr = br[k], si = bi[k];
+    T sr = br[k], si = bi[k];
 #pragma unroll
     for (int m = 0; m < k; ++m) {
       sr -= Lr[k][m] * br[m] - Li[k][m] * bi[m];
@@ -244,7 +260,7 @@ __device__ inline void cholesky_solve(const float (&Lr)[I][I], const float (&Li)
   }
 #pragma unroll
   for (int k = I - 1; k >= 0; --k) {
-    float sr = br[k], si = bi[k];
+    T sr = br[k], si = bi[k];
 #pragma unroll
     for (int m = k + 1; m < I; ++m) {
       // conj(L[m][k]) * b[m]
@@ -257,17 +273,17 @@ __device__ inline void cholesky_solve(const float (&Lr)[I][I], const float (&Li)
 
 // Inverse of a Hermitian PD matrix (upper triangle in A) from its Cholesky
 // factor: full matrix written to Xr/Xi.  Returns false if not PD.
-template <int I>
-__device__ inline bool herm_inverse(const float (&Ar)[I][I], const float (&Ai)[I][I],
-                                    float (&Xr)[I][I], float (&Xi)[I][I]) {
-  float Lr[I][I], Li[I][I], dinv[I];
-  const bool ok = cholesky<I>(Ar, Ai, Lr, Li, dinv);
+template <int I, typename T = float>
+__device__ inline bool herm_inverse(const T (&Ar)[I][I], const T (&Ai)[I][I],
+                                    T (&Xr)[I][I], T (&Xi)[I][I]) {
+  T Lr[I][I], Li[I][I], dinv[I];
+  const bool ok = cholesky<I, T>(Ar, Ai, Lr, Li, dinv);
 #pragma unroll
   for (int c = 0; c < I; ++c) {
-    float br[I], bi[I];
+    T br[I], bi[I];
 #pragma unroll
-    for (int k = 0; k < I; ++k) { br[k] = (k == c) ? 1.0f : 0.0f; bi[k] = 0.0f; }
-    cholesky_solve<I>(Lr, Li, dinv, br, bi);
+    for (int k = 0; k < I; ++k) { br[k] = (k == c) ? T(1) : T(0); bi[k] = T(0); }
+    cholesky_solve<I, T>(Lr, Li, dinv, br, bi);
 #pragma unroll
     for (int k = 0; k < I; ++k) { Xr[k][c] = br[k]; Xi[k][c] = bi[k]; }
   }
@@ -280,44 +296,44 @@ __device__ inline bool herm_inverse(const float (&Ar)[I][I], const float (&Ai)[I
 
 // Column c of P^-H.  I <= 3: cofactors, (P^-H)_kc = conj(C_kc / det P) with
 // C_kc the (k, c) cofactor of P; larger I: LU solve of P^H b = e_c.
-template <int I>
-__device__ __forceinline__ void pinvh_column(const float (&Pr)[I][I], const float (&Pi)[I][I], int c,
-                                             float (&br)[I], float (&bi)[I]) {
+template <int I, typename T = float>
+__device__ __forceinline__ void pinvh_column(const T (&Pr)[I][I], const T (&Pi)[I][I], int c,
+                                             T (&br)[I], T (&bi)[I]) {
   if constexpr (I <= 3) {
-    float Cr[I][I], Ci[I][I];
+    T Cr[I][I], Ci[I][I];
 #pragma unroll
     for (int k = 0; k < I; ++k)
 #pragma unroll
       for (int l = 0; l < I; ++l) {
         if constexpr (I == 1) {
-          Cr[k][l] = 1.f; Ci[k][l] = 0.f;
+          Cr[k][l] = T(1); Ci[k][l] = T(0);
         } else if constexpr (I == 2) {
           const int r = 1 - k, q = 1 - l;
-          const float sg = ((k + l) & 1) ? -1.f : 1.f;
+          const T sg = ((k + l) & 1) ? -T(1) : T(1);
           Cr[k][l] = sg * Pr[r][q]; Ci[k][l] = sg * Pi[r][q];
         } else {
           const int r0 = (k == 0) ? 1 : 0, r1 = (k == 2) ? 1 : 2;
           const int q0 = (l == 0) ? 1 : 0, q1 = (l == 2) ? 1 : 2;
           // m[r0][q0] m[r1][q1] - m[r0][q1] m[r1][q0]
-          float dr = Pr[r0][q0] * Pr[r1][q1] - Pi[r0][q0] * Pi[r1][q1];
-          float di = Pr[r0][q0] * Pi[r1][q1] + Pi[r0][q0] * Pr[r1][q1];
+          T dr = Pr[r0][q0] * Pr[r1][q1] - Pi[r0][q0] * Pi[r1][q1];
+          T di = Pr[r0][q0] * Pi[r1][q1] + Pi[r0][q0] * Pr[r1][q1];
           dr -= Pr[r0][q1] * Pr[r1][q0] - Pi[r0][q1] * Pi[r1][q0];
           di -= Pr[r0][q1] * Pi[r1][q0] + Pi[r0][q1] * Pr[r1][q0];
-          const float sg = ((k + l) & 1) ? -1.f : 1.f;
+          const T sg = ((k + l) & 1) ? -T(1) : T(1);
           Cr[k][l] = sg * dr; Ci[k][l] = sg * di;
         }
       }
-    float detr = 0.f, deti = 0.f;  // expansion along column 0
+    T detr = T(0), deti = T(0);  // expansion along column 0
 #pragma unroll
     for (int k = 0; k < I; ++k) {
       detr += Pr[k][0] * Cr[k][0] - Pi[k][0] * Ci[k][0];
       deti += Pr[k][0] * Ci[k][0] + Pi[k][0] * Cr[k][0];
     }
-    const float id = rcp(detr * detr + deti * deti);
-    const float qr = detr * id, qi = -deti * id;  // 1 / det
+    const T id = rcpT(detr * detr + deti * deti);
+    const T qr = detr * id, qi = -deti * id;  // 1 / det
 #pragma unroll
     for (int k = 0; k < I; ++k) {
-      float cr = Cr[k][0], ci = Ci[k][0];
+      T cr = Cr[k][0], ci = Ci[k][0];
 #pragma unroll
       for (int l = 1; l < I; ++l) {
         cr = (c == l) ? Cr[k][l] : cr;
@@ -327,95 +343,185 @@ __device__ __forceinline__ void pinvh_column(const float (&Pr)[I][I], const floa
       bi[k] = -(cr * qi + ci * qr);
     }
   } else {
-    float Mr[I][I], Mi[I][I];
+    T Mr[I][I], Mi[I][I];
 #pragma unroll
     for (int r = 0; r < I; ++r)
 #pragma unroll
       for (int k = 0; k < I; ++k) { Mr[r][k] = Pr[k][r]; Mi[r][k] = -Pi[k][r]; }
 #pragma unroll
-    for (int r = 0; r < I; ++r) { br[r] = (r == c) ? 1.f : 0.f; bi[r] = 0.f; }
-    lu_solve<I>(Mr, Mi, br, bi);
+    for (int r = 0; r < I; ++r) { br[r] = (r == c) ? T(1) : T(0); bi[r] = T(0); }
+    lu_solve<I, T>(Mr, Mi, br, bi);
   }
 }
 
-// Solve Q p = b for a Hermitian positive-definite Q given by its upper
-// triangle (Qr[a][b], Qi[a][b] for a <= b).  I <= 3: adjugate / determinant;
-// larger I: Cholesky.  b is overwritten with p.
-template <int I>
-__device__ __forceinline__ void herm_solve(const float (&Qr)[I][I], const float (&Qi)[I][I],
-                                           float (&br)[I], float (&bi)[I]) {
+// Column c of P^-H (c may differ between lanes) from single-precision P,
+// computed in precision T.  Row c of P^-1 is the vector w with w^T P_l = 0
+// for l != c and w^T P_c = 1 (bilinear, no conjugation), and [P^-H]_c is
+// conj(w).  For I <= 3 the unnormalised w is the other column turned by a
+// quarter (I = 2) or the cross product of the two other columns (I = 3);
+// dividing by w^T P_c normalises it, whatever the order of the columns.  The
+// columns are picked in single precision and widened afterwards.  Larger I:
+// LU solve in T.
+// A value the optimiser cannot trace back to the array element it came from:
+// selects between such values stay register selects instead of becoming a
+// lane-dependent index into a private (scratch) copy of the array.
+__device__ __forceinline__ float opaque(float x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
+template <int I, typename T>
+__device__ __forceinline__ void pinvh_col(const float (&Pr)[I][I], const float (&Pi)[I][I], int c,
+                                          T (&br)[I], T (&bi)[I]) {
   if constexpr (I == 1) {
-    const float iq = rcp(Qr[0][0]);
+    const T pr = Pr[0][0], pi = Pi[0][0];
+    const T id = rcpT(pr * pr + pi * pi);
+    br[0] = pr * id; bi[0] = pi * id;  // conj(1 / p) = p / |p|^2
+  } else if constexpr (I <= 3) {
+    float Mr[I][I], Mi[I][I];
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) { Mr[a][b] = opaque(Pr[a][b]); Mi[a][b] = opaque(Pi[a][b]); }
+    T pr[I], pi[I], wr[I], wi[I];
+    if constexpr (I == 2) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        pr[k] = (c == 0) ? Mr[k][0] : Mr[k][1];
+        pi[k] = (c == 0) ? Mi[k][0] : Mi[k][1];
+      }
+      const T a0r = (c == 0) ? Mr[0][1] : Mr[0][0], a0i = (c == 0) ? Mi[0][1] : Mi[0][0];
+      const T a1r = (c == 0) ? Mr[1][1] : Mr[1][0], a1i = (c == 0) ? Mi[1][1] : Mi[1][0];
+      wr[0] = a1r; wi[0] = a1i; wr[1] = -a0r; wi[1] = -a0i;
+    } else {
+      T ar[3], ai[3], er[3], ei[3];  // the two other columns, in index order
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        pr[k] = (c == 0) ? Mr[k][0] : ((c == 1) ? Mr[k][1] : Mr[k][2]);
+        pi[k] = (c == 0) ? Mi[k][0] : ((c == 1) ? Mi[k][1] : Mi[k][2]);
+        ar[k] = (c == 0) ? Mr[k][1] : Mr[k][0];
+        ai[k] = (c == 0) ? Mi[k][1] : Mi[k][0];
+        er[k] = (c == 2) ? Mr[k][1] : Mr[k][2];
+        ei[k] = (c == 2) ? Mi[k][1] : Mi[k][2];
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        // w_k = a_k1 e_k2 - a_k2 e_k1
+        wr[k] = (ar[k1] * er[k2] - ai[k1] * ei[k2]) - (ar[k2] * er[k1] - ai[k2] * ei[k1]);
+        wi[k] = (ar[k1] * ei[k2] + ai[k1] * er[k2]) - (ar[k2] * ei[k1] + ai[k2] * er[k1]);
+      }
+    }
+    T sr = T(0), si = T(0);  // s = w^T P_c
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      sr += wr[k] * pr[k] - wi[k] * pi[k];
+      si += wr[k] * pi[k] + wi[k] * pr[k];
+    }
+    const T id = rcpT(sr * sr + si * si);
+    const T qr = sr * id, qi = -si * id;  // 1 / s
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      br[k] = wr[k] * qr - wi[k] * qi;    // conj(w / s)
+      bi[k] = -(wr[k] * qi + wi[k] * qr);
+    }
+  } else {
+    T Pdr[I][I], Pdi[I][I];
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) { Pdr[a][b] = Pr[a][b]; Pdi[a][b] = Pi[a][b]; }
+    pinvh_column<I, T>(Pdr, Pdi, c, br, bi);
+  }
+}
+
+
+// Solve Q p = b for a Hermitian positive-definite Q given by its upper
+// triangle (Qr[a][b], Qi[a][b] for a <= b).  I <= 2: adjugate / determinant;
+// I = 3: LDL^H; larger I: Cholesky.  b is overwritten with p.
+//
+// Why not the 3x3 adjugate: near DC a diffuse field makes Q nearly rank one.
+// The 2x2 minors of such a matrix cancel to O(lambda_1 lambda_2) from terms
+// of O(lambda_1^2), and combining them cancels again, so the adjugate solve
+// loses about cond(Q)^2 eps (1e-3 in single precision at cond ~ 1e3), while
+// an LDL^H or Cholesky factorisation loses cond(Q) eps.  For I = 2 the
+// adjugate entries are entries of Q and only the determinant cancels, which
+// also costs cond(Q) eps.
+template <int I, typename T = float>
+__device__ __forceinline__ void herm_solve(const T (&Qr)[I][I], const T (&Qi)[I][I],
+                                           T (&br)[I], T (&bi)[I]) {
+  if constexpr (I == 1) {
+    const T iq = rcpT(Qr[0][0]);
     br[0] *= iq; bi[0] *= iq;
   } else if constexpr (I == 2) {
-    const float a = Qr[0][0], d = Qr[1][1], xr = Qr[0][1], xi = Qi[0][1];
-    const float idet = rcp(a * d - (xr * xr + xi * xi));
+    const T a = Qr[0][0], d = Qr[1][1], xr = Qr[0][1], xi = Qi[0][1];
+    const T idet = rcpT(a * d - (xr * xr + xi * xi));
     // adj = [[d, -x], [-conj(x), a]]
-    const float p0r = d * br[0] - (xr * br[1] - xi * bi[1]);
-    const float p0i = d * bi[0] - (xr * bi[1] + xi * br[1]);
-    const float p1r = a * br[1] - (xr * br[0] + xi * bi[0]);
-    const float p1i = a * bi[1] - (xr * bi[0] - xi * br[0]);
+    const T p0r = d * br[0] - (xr * br[1] - xi * bi[1]);
+    const T p0i = d * bi[0] - (xr * bi[1] + xi * br[1]);
+    const T p1r = a * br[1] - (xr * br[0] + xi * bi[0]);
+    const T p1i = a * bi[1] - (xr * bi[0] - xi * br[0]);
     br[0] = p0r * idet; bi[0] = p0i * idet; br[1] = p1r * idet; bi[1] = p1i * idet;
   } else if constexpr (I == 3) {
-    // Q = [[a, x, y], [x*, d, z], [y*, z*, g]] with a, d, g real.
-    const float a = Qr[0][0], d = Qr[1][1], g = Qr[2][2];
-    const float xr = Qr[0][1], xi = Qi[0][1], yr = Qr[0][2], yi = Qi[0][2], zr = Qr[1][2], zi = Qi[1][2];
-    const float x2 = xr * xr + xi * xi, y2 = yr * yr + yi * yi, z2 = zr * zr + zi * zi;
-    // adjugate (Hermitian): diagonal and upper entries
-    const float A00 = d * g - z2, A11 = a * g - y2, A22 = a * d - x2;
-    // A01 = y conj(z) - x g
-    const float A01r = (yr * zr + yi * zi) - xr * g, A01i = (yi * zr - yr * zi) - xi * g;
-    // A02 = x z - y d
-    const float A02r = (xr * zr - xi * zi) - yr * d, A02i = (xr * zi + xi * zr) - yi * d;
-    // A12 = y conj(x) - a z
-    const float A12r = (yr * xr + yi * xi) - a * zr, A12i = (yi * xr - yr * xi) - a * zi;
-    // det = a A00 + 2 Re(x conj? ...) computed as a A00 + Re(x A10 + y A20) with A10 = conj(A01), A20 = conj(A02)
-    const float det = a * A00 + (xr * A01r + xi * A01i) + (yr * A02r + yi * A02i);
-    const float idet = rcp(det);
-    const float b0r = br[0], b0i = bi[0], b1r = br[1], b1i = bi[1], b2r = br[2], b2i = bi[2];
-    // p0 = A00 b0 + A01 b1 + A02 b2
-    br[0] = (A00 * b0r + (A01r * b1r - A01i * b1i) + (A02r * b2r - A02i * b2i)) * idet;
-    bi[0] = (A00 * b0i + (A01r * b1i + A01i * b1r) + (A02r * b2i + A02i * b2r)) * idet;
-    // p1 = conj(A01) b0 + A11 b1 + A12 b2
-    br[1] = ((A01r * b0r + A01i * b0i) + A11 * b1r + (A12r * b2r - A12i * b2i)) * idet;
-    bi[1] = ((A01r * b0i - A01i * b0r) + A11 * b1i + (A12r * b2i + A12i * b2r)) * idet;
-    // p2 = conj(A02) b0 + conj(A12) b1 + A22 b2
-    br[2] = ((A02r * b0r + A02i * b0i) + (A12r * b1r + A12i * b1i) + A22 * b2r) * idet;
-    bi[2] = ((A02r * b0i - A02i * b0r) + (A12r * b1i - A12i * b1r) + A22 * b2i) * idet;
+    // Q = L D L^H, L unit lower triangular; with Q = [[a, x, y], [., d, z],
+    // [., ., g]] the lower entries are conj(x), conj(y), conj(z).
+    const T x_r = Qr[0][1], x_i = Qi[0][1], y_r = Qr[0][2], y_i = Qi[0][2];
+    const T z_r = Qr[1][2], z_i = Qi[1][2];
+    const T d0 = Qr[0][0], id0 = rcpT(d0);
+    const T l10r = x_r * id0, l10i = -x_i * id0;  // L10 = conj(x) / d0
+    const T l20r = y_r * id0, l20i = -y_i * id0;  // L20 = conj(y) / d0
+    const T d1 = Qr[1][1] - d0 * (l10r * l10r + l10i * l10i), id1 = rcpT(d1);
+    // L21 = (conj(z) - d0 L20 conj(L10)) / d1
+    const T t_r = z_r - d0 * (l20r * l10r + l20i * l10i);
+    const T t_i = -z_i - d0 * (l20i * l10r - l20r * l10i);
+    const T l21r = t_r * id1, l21i = t_i * id1;
+    const T d2 = Qr[2][2] - d0 * (l20r * l20r + l20i * l20i) - d1 * (l21r * l21r + l21i * l21i);
+    const T id2 = rcpT(d2);
+    // L w = b
+    const T w0r = br[0], w0i = bi[0];
+    const T w1r = br[1] - (l10r * w0r - l10i * w0i), w1i = bi[1] - (l10r * w0i + l10i * w0r);
+    const T w2r = br[2] - (l20r * w0r - l20i * w0i) - (l21r * w1r - l21i * w1i);
+    const T w2i = bi[2] - (l20r * w0i + l20i * w0r) - (l21r * w1i + l21i * w1r);
+    // L^H p = D^-1 w
+    const T p2r = w2r * id2, p2i = w2i * id2;
+    const T p1r = w1r * id1 - (l21r * p2r + l21i * p2i), p1i = w1i * id1 - (l21r * p2i - l21i * p2r);
+    br[0] = w0r * id0 - (l10r * p1r + l10i * p1i) - (l20r * p2r + l20i * p2i);
+    bi[0] = w0i * id0 - (l10r * p1i - l10i * p1r) - (l20r * p2i - l20i * p2r);
+    br[1] = p1r; bi[1] = p1i; br[2] = p2r; bi[2] = p2i;
   } else {
-    float Lr[I][I], Li[I][I], dinv[I];
-    cholesky<I>(Qr, Qi, Lr, Li, dinv);
-    cholesky_solve<I>(Lr, Li, dinv, br, bi);
+    T Lr[I][I], Li[I][I], dinv[I];
+    cholesky<I, T>(Qr, Qi, Lr, Li, dinv);
+    cholesky_solve<I, T>(Lr, Li, dinv, br, bi);
   }
 }
 
 // Inverse of a Hermitian positive-definite matrix given by its upper triangle
 // (full result in Xr/Xi).  I <= 3: adjugate / determinant; larger I:
 // Cholesky.
-template <int I>
-__device__ __forceinline__ void herm_inv(const float (&Ar)[I][I], const float (&Ai)[I][I],
-                                         float (&Xr)[I][I], float (&Xi)[I][I]) {
+template <int I, typename T = float>
+__device__ __forceinline__ void herm_inv(const T (&Ar)[I][I], const T (&Ai)[I][I],
+                                         T (&Xr)[I][I], T (&Xi)[I][I]) {
   if constexpr (I == 1) {
-    Xr[0][0] = rcp(Ar[0][0]); Xi[0][0] = 0.f;
+    Xr[0][0] = rcpT(Ar[0][0]); Xi[0][0] = T(0);
   } else if constexpr (I == 2) {
-    const float a = Ar[0][0], d = Ar[1][1], xr = Ar[0][1], xi = Ai[0][1];
-    const float id = rcp(a * d - (xr * xr + xi * xi));
-    Xr[0][0] = d * id; Xi[0][0] = 0.f; Xr[1][1] = a * id; Xi[1][1] = 0.f;
+    const T a = Ar[0][0], d = Ar[1][1], xr = Ar[0][1], xi = Ai[0][1];
+    const T id = rcpT(a * d - (xr * xr + xi * xi));
+    Xr[0][0] = d * id; Xi[0][0] = T(0); Xr[1][1] = a * id; Xi[1][1] = T(0);
     Xr[0][1] = -xr * id; Xi[0][1] = -xi * id; Xr[1][0] = -xr * id; Xi[1][0] = xi * id;
   } else if constexpr (I == 3) {
-    const float a = Ar[0][0], d = Ar[1][1], g = Ar[2][2];
-    const float xr = Ar[0][1], xi = Ai[0][1], yr = Ar[0][2], yi = Ai[0][2], zr = Ar[1][2], zi = Ai[1][2];
-    const float A00 = d * g - (zr * zr + zi * zi), A11 = a * g - (yr * yr + yi * yi), A22 = a * d - (xr * xr + xi * xi);
-    const float A01r = (yr * zr + yi * zi) - xr * g, A01i = (yi * zr - yr * zi) - xi * g;
-    const float A02r = (xr * zr - xi * zi) - yr * d, A02i = (xr * zi + xi * zr) - yi * d;
-    const float A12r = (yr * xr + yi * xi) - a * zr, A12i = (yi * xr - yr * xi) - a * zi;
-    const float id = rcp(a * A00 + (xr * A01r + xi * A01i) + (yr * A02r + yi * A02i));
-    Xr[0][0] = A00 * id; Xi[0][0] = 0.f; Xr[1][1] = A11 * id; Xi[1][1] = 0.f; Xr[2][2] = A22 * id; Xi[2][2] = 0.f;
+    const T a = Ar[0][0], d = Ar[1][1], g = Ar[2][2];
+    const T xr = Ar[0][1], xi = Ai[0][1], yr = Ar[0][2], yi = Ai[0][2], zr = Ar[1][2], zi = Ai[1][2];
+    const T A00 = d * g - (zr * zr + zi * zi), A11 = a * g - (yr * yr + yi * yi), A22 = a * d - (xr * xr + xi * xi);
+    const T A01r = (yr * zr + yi * zi) - xr * g, A01i = (yi * zr - yr * zi) - xi * g;
+    const T A02r = (xr * zr - xi * zi) - yr * d, A02i = (xr * zi + xi * zr) - yi * d;
+    const T A12r = (yr * xr + yi * xi) - a * zr, A12i = (yi * xr - yr * xi) - a * zi;
+    const T id = rcpT(a * A00 + (xr * A01r + xi * A01i) + (yr * A02r + yi * A02i));
+    Xr[0][0] = A00 * id; Xi[0][0] = T(0); Xr[1][1] = A11 * id; Xi[1][1] = T(0); Xr[2][2] = A22 * id; Xi[2][2] = T(0);
     Xr[0][1] = A01r * id; Xi[0][1] = A01i * id; Xr[1][0] = A01r * id; Xi[1][0] = -A01i * id;
     Xr[0][2] = A02r * id; Xi[0][2] = A02i * id; Xr[2][0] = A02r * id; Xi[2][0] = -A02i * id;
     Xr[1][2] = A12r * id; Xi[1][2] = A12i * id; Xr[2][1] = A12r * id; Xi[2][1] = -A12i * id;
   } else {
-    herm_inverse<I>(Ar, Ai, Xr, Xi);
+    herm_inverse<I, T>(Ar, Ai, Xr, Xi);
   }
 }
 

@@ -9,7 +9,8 @@ namespace fca {
 const KernelSet* FCA_CAT4(kernel_set_I, FCA_I, _J, FCA_J)() {
   static const KernelSet set = {
       &launch_as_iter_stream<FCA_I, FCA_J>, &launch_as_iter_resident<FCA_I, FCA_J>,
-      &as_resident_fits<FCA_I, FCA_J>,      &launch_em_iter<FCA_I, FCA_J>,
+      &as_resident_fits<FCA_I, FCA_J>,      &launch_as_batch_resident<FCA_I, FCA_J>,
+      &launch_em_iter<FCA_I, FCA_J>,
       &launch_em_iter_resident<FCA_I, FCA_J>, &em_resident_fits<FCA_I, FCA_J>,
       &launch_as_loglik<FCA_I, FCA_J>,      &launch_em_loglik<FCA_I, FCA_J>,
       &launch_as_wiener<FCA_I, FCA_J>,      &launch_em_wiener<FCA_I, FCA_J>,

@@ -1,0 +1,42 @@
+// Internal definitions shared by the C ABI implementation files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "fastfca.h"
+#include "fca_state.h"
+
+struct fca_ctx {
+  fca_method method;
+  int F, N, I, J;
+  hipStream_t stream;
+  const fca::KernelSet* ks;
+  fca::DevState s;
+  void* arena;
+  int check_finite;
+  int path;   // 0 auto, 1 resident, 2 streaming
+  int waves;  // 0 auto
+  int bpw;    // bins per workgroup of the resident AS kernel, 0 auto
+  int autotune;  // 1: time the candidate launch shapes once per (method, I, J, F, N)
+  float* backup;  // state copy used while tuning: vs, lam, P (AS) or vs, R (EM)
+  int last_waves, last_bpw;  // launch shape of the last iterate call (waves 0: streaming)
+  std::string err;
+};
+
+namespace fca {
+// Save the iterated state of a context to its backup region, or restore it.
+hipError_t copy_state(fca_ctx* c, bool save);
+
+// The host-side argument checks of fca_init (no device access).
+fca_status validate_init(fca_method method, int F, int N, int I, int J, const void* x, const void* v0,
+                         const void* lam0, const void* P0, const void* R0, std::string* msg);
+
+// Persistent launch-shape cache (fca_tunecache.cpp), active when the
+// environment variable FASTFCA_TUNE_CACHE names a file.  Keys should start
+// with tune_key_prefix() (device architecture, CU count, library build).
+std::string tune_key_prefix();
+bool tune_cache_get(const std::string& key, int* a, int* b);
+void tune_cache_put(const std::string& key, int a, int b);
+}  // namespace fca

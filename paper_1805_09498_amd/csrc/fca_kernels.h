@@ -113,6 +113,20 @@ __device__ __forceinline__ void as_point_weights(const float (&lam)[J][I], const
 // Packed Hermitian slot layout of an I x I matrix in I*I reals: slot (a, b)
 // with a <= b holds Re A_ab, slot (b, a) with a < b holds Im A_ab.
 // Adds w * x x^H, i.e. A_ab += w x_a conj(x_b).
+// z = y y^H in the packed Hermitian layout of herm_rank1_acc.
+template <int I>
+__device__ __forceinline__ void herm_outer(float (&z)[I * I], const float (&yr)[I], const float (&yi)[I]) {
+#pragma unroll
+  for (int a = 0; a < I; ++a) {
+    z[a * I + a] = fmaf(yr[a], yr[a], yi[a] * yi[a]);
+#pragma unroll
+    for (int b = a + 1; b < I; ++b) {
+      z[a * I + b] = fmaf(yr[a], yr[b], yi[a] * yi[b]);
+      z[b * I + a] = fmaf(yi[a], yr[b], -yr[a] * yi[b]);
+    }
+  }
+}
+
 template <int I>
 __device__ __forceinline__ void herm_rank1_acc(float (&A)[I * I], float w, const float (&xr)[I],
                                                const float (&xi)[I]) {
@@ -230,17 +244,27 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
 #pragma unroll
     for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
 
+  // the old P (k_as_solve replaces it after this pass)
+  float Pr[I][I], Pi[I][I];
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      const float2 t = s.P[(size_t)f * I * I + a * I + b];
+      Pr[a][b] = t.x; Pi[a][b] = t.y;
+    }
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   const float* vf = s.vs + (size_t)f * J * s.Npad;
-  float xr[kPts][I], xi[kPts][I], w[kPts][I];
+  float yr[kPts][I], yi[kPts][I], w[kPts][I];
 #pragma unroll
   for (int p = 0; p < kPts; ++p) {
     const int n = chunk * kChunk + p * kBlock + threadIdx.x;
     const bool ok = n < s.N;
     const int nn = ok ? n : 0;
-    float v[J];
+    float v[J], xr[I], xi[I];
 #pragma unroll
-    for (int i = 0; i < I; ++i) { xr[p][i] = xf[(size_t)i * s.Npad + nn]; xi[p][i] = xf[(size_t)(I + i) * s.Npad + nn]; }
+    for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
+    as_transform<I>(Pr, Pi, xr, xi, yr[p], yi[p]);
 #pragma unroll
     for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
     float wp[I];
@@ -255,21 +279,33 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
 #pragma unroll
     for (int k = 0; k < I * I; ++k) A[k] = 0.f;
 #pragma unroll
-    for (int p = 0; p < kPts; ++p) herm_rank1_acc<I>(A, w[p][i], xr[p], xi[p]);
+    for (int p = 0; p < kPts; ++p) herm_rank1_acc<I>(A, w[p][i], yr[p], yi[p]);
     block_sum_store<I * I>(A, out + i * I * I, red);
   }
 }
 
-// One lane per (bin, column); 8 bins per 64-lane workgroup.
+// One lane per (bin, column); 8 bins per 64-lane workgroup.  Eq. 23 in the
+// basis of y = P^H x (as in the resident kernel): column i of
+// A = P_old^-1 P_new solves S_i a = N e_i with S_i = N G_i the tile sums of
+// pass B, K > 1 iterates a_i = N S_i^-1 [A^-H]_i from A = 1, and
+// P_new = P_old A.
 template <int I, int J>
 __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
   const int fl = threadIdx.x / 8, i = threadIdx.x % 8;
   const int f = blockIdx.x * 8 + fl;
   const bool act = (f < s.F) && (i < I);
-  __shared__ float sPr[8][I][I], sPi[8][I][I];
-  const float invN = 1.0f / float(s.N);
-  float Qr[I][I], Qi[I][I];
+  __shared__ float sAr[8][I][I], sAi[8][I][I];
+  const float invN = 1.0f / float(s.N), fN = float(s.N);
+  float Sr[I][I], Si[I][I], Pr[I][I], Pi[I][I];
   if (act) {
+    // the old P (every lane of a bin reads it before any lane writes)
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) {
+        const float2 t = s.P[(size_t)f * I * I + a * I + b];
+        Pr[a][b] = t.x; Pi[a][b] = t.y;
+      }
     // lambda update (eq. 20): column i of every Lambda_j.
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -278,7 +314,7 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
       float* l = s.lam + (size_t)f * J * I + j * I + i;
       *l = acc * (float(I) * (*l) * invN);  // eq. 20 (old lambda times the scaled sum)
     }
-    // Q_i of eq. 23 from the tile partials.
+    // S_i from the tile partials.
     float A[I * I];
 #pragma unroll
     for (int k = 0; k < I * I; ++k) A[k] = 0.f;
@@ -289,41 +325,53 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
     }
 #pragma unroll
     for (int a = 0; a < I; ++a) {
-      Qr[a][a] = A[a * I + a] * invN; Qi[a][a] = 0.f;
+      Sr[a][a] = A[a * I + a]; Si[a][a] = 0.f;
 #pragma unroll
       for (int b = a + 1; b < I; ++b) {
-        Qr[a][b] = A[a * I + b] * invN; Qi[a][b] = A[b * I + a] * invN;
-        Qr[b][a] = Qr[a][b]; Qi[b][a] = -Qi[a][b];
+        Sr[a][b] = A[a * I + b]; Si[a][b] = A[b * I + a];
+        Sr[b][a] = Sr[a][b]; Si[b][a] = -Si[a][b];
       }
     }
-#pragma unroll
-    for (int a = 0; a < I; ++a) {
-      const float2 t = s.P[(size_t)f * I * I + a * I + i];
-      sPr[fl][a][i] = t.x; sPi[fl][a][i] = t.y;
-    }
   }
-  __syncthreads();
   for (int kk = 0; kk < s.K; ++kk) {
-    float pr[I], pi[I];
+    float ar[I], ai[I];
     if (act) {
-      float Pr[I][I], Pi[I][I];
+      if (kk == 0) {
 #pragma unroll
-      for (int a = 0; a < I; ++a)
+        for (int a = 0; a < I; ++a) { ar[a] = (a == i) ? fN : 0.f; ai[a] = 0.f; }
+      } else {
+        float Ar[I][I], Ai[I][I];
 #pragma unroll
-        for (int b = 0; b < I; ++b) { Pr[a][b] = sPr[fl][a][b]; Pi[a][b] = sPi[fl][a][b]; }
-      pinvh_column<I>(Pr, Pi, i, pr, pi);   // b_i = column i of P^-H
-      herm_solve<I>(Qr, Qi, pr, pi);        // p_i = Q_i^-1 b_i
+        for (int a = 0; a < I; ++a)
+#pragma unroll
+          for (int b = 0; b < I; ++b) { Ar[a][b] = sAr[fl][a][b]; Ai[a][b] = sAi[fl][a][b]; }
+        pinvh_col<I, float>(Ar, Ai, i, ar, ai);   // column i of A^-H
+#pragma unroll
+        for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
+      }
+      herm_solve<I>(Sr, Si, ar, ai);
     }
     __syncthreads();
     if (act) {
 #pragma unroll
-      for (int a = 0; a < I; ++a) { sPr[fl][a][i] = pr[a]; sPi[fl][a][i] = pi[a]; }
+      for (int a = 0; a < I; ++a) { sAr[fl][a][i] = ar[a]; sAi[fl][a][i] = ai[a]; }
     }
     __syncthreads();
   }
   if (act) {
+    // column i of P_new = P_old A
 #pragma unroll
-    for (int a = 0; a < I; ++a) s.P[(size_t)f * I * I + a * I + i] = make_float2(sPr[fl][a][i], sPi[fl][a][i]);
+    for (int a = 0; a < I; ++a) {
+      float pr = 0.f, pi = 0.f;
+#pragma unroll
+      for (int b = 0; b < I; ++b) {
+        pr = fmaf(Pr[a][b], sAr[fl][b][i], pr);
+        pr = fmaf(-Pi[a][b], sAi[fl][b][i], pr);
+        pi = fmaf(Pr[a][b], sAi[fl][b][i], pi);
+        pi = fmaf(Pi[a][b], sAr[fl][b][i], pi);
+      }
+      s.P[(size_t)f * I * I + a * I + i] = make_float2(pr, pi);
+    }
   }
 }
 

@@ -7,10 +7,20 @@
 // lambda and P back at the end.  Lane t of a workgroup with T lanes owns
 // frames n = t, t + T, ..., t + (NPT-1) T (coalesced loads and stores).
 //
-// Per iteration:  phase A (per point, eq. 15-19) -> transposed wave sums of
-// the eq. 20 summands -> LDS -> lambda (eq. 20) in every lane -> phase B (per
-// point weights and the sums of eq. 23) -> transposed wave sums -> LDS ->
-// lanes 0..I-1 of wave 0 each solve one column of eq. 23 -> P in LDS.
+// Per iteration:  phase A (per point y = P^H x, eq. 15-19) -> transposed
+// wave sums of the eq. 20 summands -> LDS -> lambda (eq. 20) in every lane ->
+// phase B (per point weights and the weighted sums of y y^H) -> transposed
+// wave sums -> LDS -> lanes 0..I-1 of wave 0 each solve one column of eq. 23
+// in the basis of y -> P in LDS.
+//
+// Eq. 23 in the basis of y.  With y = P^H x the weighted covariance of
+// eq. 23 is Q_i = P^-H G_i P^-1, G_i = (1/N) sum_n y y^H / d_i, so the
+// update p_i = Q_i^-1 [P^-H]_i equals P G_i^-1 e_i exactly: column i of
+// A = P_old^-1 P_new solves G_i a = e_i and P_new = P_old A.  Near DC a
+// diffuse field makes Q_i nearly singular (condition ~1e4), and rounding its
+// single-precision sums costs ~1e-4 in P; P has already absorbed that
+// structure, so G_i stays well conditioned and no inverse of P is needed.
+// Further fixed-point steps (K > 1) iterate the same map on A from A = 1.
 #pragma once
 
 #include "fca_kernels.h"
@@ -19,6 +29,12 @@ namespace fca {
 
 constexpr int kResMaxBlock = 256;
 constexpr int kResMaxWaves = kResMaxBlock / kWave;
+
+// Up to I = 4 the workgroup keeps x in registers next to y = P^H x; beyond,
+// it reads x again each iteration, which leaves room for more frames per lane
+// (the largest configurations spend ~I^3 flops per point and byte of x).
+template <int I>
+constexpr bool kResXInRegs = (I <= 4);
 
 // Sum of the per-wave partials part[w * stride + k] over the nw waves (the
 // loop is unrolled to the maximum wave count; nw is uniform).
@@ -30,19 +46,18 @@ __device__ __forceinline__ float sum_waves(const float* part, int stride, int k,
   return t;
 }
 
+// The body of one frequency-resident workgroup: bins f0 .. f0 + nb - 1 of the
+// problem s (nb in {1, 2}), n_iter hybrid iterations.
 template <int I, int J, int NPT>
-__global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_iter, int bpw) {
+__device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int nb, int n_iter) {
   constexpr int VS = pad4(J * I);
   constexpr bool kOnePass = I * I * I <= 64;       // all I weighted sums in one sweep
   constexpr int VQ = kOnePass ? pad4(I * I * I) : pad4(I * I);
   constexpr int QSTRIDE = kOnePass ? VQ : I * VQ;  // per-wave stride of the Q partials
-  // keep x x^H per point in registers when it fits (it never changes)
-  constexpr bool kZ = (I <= 4) && (NPT * (3 * I + J + I * I) <= 224);
-  // A workgroup of W waves owns nb = min(bpw, bins left) bins with W / nb
-  // waves each (bpw in {1, 2}); the waves of one bin are consecutive.
+  constexpr bool kXReg = kResXInRegs<I>;
+  // A workgroup of W waves owns nb bins with W / nb waves each; the waves of
+  // one bin are consecutive.
   const int W = blockDim.x / kWave;
-  const int f0 = blockIdx.x * bpw;
-  const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
   const int nw = W / nb;                                   // waves per bin
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int bin = wave / nw, wl = wave % nw;               // bin in the workgroup, wave in the bin
@@ -68,24 +83,21 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   float* vf = s.vs + (size_t)f * J * s.Npad;
-  float xr[NPT][I], xi[NPT][I], v[NPT][J];
-  float z[kZ ? NPT : 1][kZ ? I * I : 1];
+  float xr[kXReg ? NPT : 1][I], xi[kXReg ? NPT : 1][I], v[NPT][J];
+  float yr[NPT][I], yi[NPT][I];  // y = P^H x of the current iteration (phase A -> B)
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tb + k * T;
     const bool ok = n < s.N;
+    if constexpr (kXReg) {
 #pragma unroll
-    for (int i = 0; i < I; ++i) {
-      xr[k][i] = ok ? xf[(size_t)i * s.Npad + n] : 0.f;
-      xi[k][i] = ok ? xf[(size_t)(I + i) * s.Npad + n] : 0.f;
+      for (int i = 0; i < I; ++i) {
+        xr[k][i] = ok ? xf[(size_t)i * s.Npad + n] : 0.f;
+        xi[k][i] = ok ? xf[(size_t)(I + i) * s.Npad + n] : 0.f;
+      }
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) v[k][j] = ok ? vf[(size_t)j * s.Npad + n] : 1.f;
-    if constexpr (kZ) {
-#pragma unroll
-      for (int q = 0; q < I * I; ++q) z[k][q] = 0.f;
-      herm_rank1_acc<I>(z[k], 1.f, xr[k], xi[k]);
-    }
   }
   __syncthreads();
   const float invN = 1.0f / float(s.N);
@@ -113,8 +125,28 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
       for (int k = 0; k < NPT; ++k) {
         if (wbase + k * T < s.N) {  // wave-uniform: skip slots no lane of the wave owns
           const bool ok = tb + k * T < s.N;
+          if constexpr (kXReg) {
+            as_transform<I>(Pr, Pi, xr[k], xi[k], yr[k], yi[k]);
+          } else {
+            // x is read again each iteration (cached; it never changes).  The
+            // slot starts below N at a multiple of 64 and Npad is a multiple of
+            // 64, so every lane reads inside the zero-padded plane: no select.
+            // The zero offset is opaque to the optimiser: otherwise it keeps
+            // the addresses of every point's loads alive across iterations.
+            float xr1[I], xi1[I];
+            int zoff = 0;
+            asm volatile("" : "+s"(zoff));
+            const float* xl = xf + zoff + tb + k * T;
+#pragma unroll
+            for (int i = 0; i < I; ++i) {
+              xr1[i] = xl[(size_t)i * s.Npad];
+              xi1[i] = xl[(size_t)(I + i) * s.Npad];
+            }
+            as_transform<I>(Pr, Pi, xr1, xi1, yr[k], yi[k]);
+          }
           float y2[I];
-          as_transform_pow<I>(Pr, Pi, xr[k], xi[k], y2);
+#pragma unroll
+          for (int i = 0; i < I; ++i) y2[i] = fmaf(yr[k][i], yr[k][i], yi[k][i] * yi[k][i]);
           as_point_em<I, J>(y2, lam, v[k], S, ok);
         }
       }
@@ -132,7 +164,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
       for (int i = 0; i < I; ++i)  // eq. 20: old lambda times the scaled sum
         lam[j][i] = sum_waves(binS, VS, j * I + i, nw) * (float(I) * lam[j][i] * invN);
 
-    // ---- phase B: weighted covariances of eq. 23 --------------------------
+    // ---- phase B: the weighted sums N G_i of y y^H (eq. 23) ----------------
     if constexpr (kOnePass) {
       float A[I][I * I];
 #pragma unroll
@@ -142,20 +174,15 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (wbase + k * T < s.N) {
-          // lanes past N hold x = 0 and their initial v (kept by phase A), so
+          // lanes past N hold y = 0 and their initial v (kept by phase A), so
           // their weight is finite and they add nothing
-          float w[I];
+          float w[I], z[I * I];
           as_point_weights<I, J>(lam, v[k], w);
+          herm_outer<I>(z, yr[k], yi[k]);
 #pragma unroll
-          for (int i = 0; i < I; ++i) {
-            const float wi = w[i];
-            if constexpr (kZ) {
+          for (int i = 0; i < I; ++i)
 #pragma unroll
-              for (int q = 0; q < I * I; ++q) A[i][q] = fmaf(wi, z[k][q], A[i][q]);
-            } else {
-              herm_rank1_acc<I>(A[i], wi, xr[k], xi[k]);
-            }
-          }
+            for (int q = 0; q < I * I; ++q) A[i][q] = fmaf(w[i], z[q], A[i][q]);
         }
       }
       float flat[I * I * I];
@@ -165,9 +192,8 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
         for (int q = 0; q < I * I; ++q) flat[i * I * I + q] = A[i][q];
       wave_totals_to_lds<I * I * I>(flat, redQ, QSTRIDE);
     } else {
-      float w[NPT][I];
-#pragma unroll
-      for (int k = 0; k < NPT; ++k) as_point_weights<I, J>(lam, v[k], w[k]);  // x = 0, v kept past N
+      // one pass over the points per column i; the weight 1 / d_i of a point
+      // is formed in each pass rather than kept for all points (registers)
 #pragma unroll
       for (int i = 0; i < I; ++i) {
         float A[I * I];
@@ -175,7 +201,12 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
         for (int q = 0; q < I * I; ++q) A[q] = 0.f;
 #pragma unroll
         for (int k = 0; k < NPT; ++k)
-          if (wbase + k * T < s.N) herm_rank1_acc<I>(A, w[k][i], xr[k], xi[k]);
+          if (wbase + k * T < s.N) {
+            float d = 0.f;  // y = 0 and v kept past N: finite, adds nothing
+#pragma unroll
+            for (int j = 0; j < J; ++j) d = fmaf(v[k][j], lam[j][i], d);
+            herm_rank1_acc<I>(A, rcp(d), yr[k], yi[k]);
+          }
         wave_totals_to_lds<I * I>(A, redQ + i * VQ, QSTRIDE);
       }
     }
@@ -189,37 +220,61 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
     // The bin's first wave solves (lane c: column c); the other waves go
     // straight to the barrier that publishes the new P.
     if (wl == 0) {
-      float Qr[I][I], Qi[I][I];
+      // S_c = N G_c (upper triangle); column c of A solves S_c a = N e_c.
+      float Sr[I][I], Si[I][I];
       const float* Qc = binQ + (kOnePass ? c * I * I : c * VQ);
 #pragma unroll
       for (int a = 0; a < I; ++a)
 #pragma unroll
         for (int b = a; b < I; ++b) {
-          Qr[a][b] = sum_waves(Qc, QSTRIDE, a * I + b, nw) * invN;
-          Qi[a][b] = (b > a) ? sum_waves(Qc, QSTRIDE, b * I + a, nw) * invN : 0.f;
+          Sr[a][b] = sum_waves(Qc, QSTRIDE, a * I + b, nw);
+          Si[a][b] = (b > a) ? sum_waves(Qc, QSTRIDE, b * I + a, nw) : 0.f;
         }
-      float br[I], bi[I];
-      pinvh_column<I>(Pr, Pi, c, br, bi);
-      herm_solve<I>(Qr, Qi, br, bi);  // p_c = Q_c^-1 [P^-H]_c
-      // K > 1: further fixed-point steps reuse Q_c; lane b holds column b of
-      // the current P, so the matrix is gathered with readlane (no LDS, no
-      // barrier: only wave 0 takes part).
+      const float fN = float(s.N);
+      float ar[I], ai[I], pnr[I], pni[I];
+#pragma unroll
+      for (int a = 0; a < I; ++a) { ar[a] = (a == c) ? fN : 0.f; ai[a] = 0.f; }
+      herm_solve<I>(Sr, Si, ar, ai);
+      // K > 1: further fixed-point steps a_c = G_c^-1 [A^-H]_c; lane b holds
+      // column b of the current A, gathered with readlane (no LDS, no
+      // barrier: only the bin's first wave takes part).  Compiled up to
+      // I = kResMaxIK only (the inverse of A costs registers that larger I
+      // cannot spare); the host sends K > 1 at larger I to the streaming
+      // kernels.
 #pragma unroll 1
-      for (int kk = 1; kk < s.K; ++kk) {
-        float P2r[I][I], P2i[I][I];
+      for (int kk = 1; kk < (I <= kResMaxIK ? s.K : 1); ++kk) {
+        float A2r[I][I], A2i[I][I];
 #pragma unroll
         for (int a = 0; a < I; ++a)
 #pragma unroll
           for (int b = 0; b < I; ++b) {
-            P2r[a][b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(br[a]), b));
-            P2i[a][b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bi[a]), b));
+            A2r[a][b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ar[a]), b));
+            A2i[a][b] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ai[a]), b));
           }
-        pinvh_column<I>(P2r, P2i, c, br, bi);
-        herm_solve<I>(Qr, Qi, br, bi);
+        pinvh_col<I, float>(A2r, A2i, c, ar, ai);
+#pragma unroll
+        for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
+        herm_solve<I>(Sr, Si, ar, ai);
+      }
+      // p_c = P_old a_c; P_old is read from LDS again (the copy in registers
+      // from phase A is not kept alive through phase B).  Lane c < I writes
+      // column c only after every lane of the wave has read row a.
+#pragma unroll
+      for (int a = 0; a < I; ++a) {
+        float pr = 0.f, pi = 0.f;
+#pragma unroll
+        for (int b = 0; b < I; ++b) {
+          const float qr = sPr[bin][a][b], qi = sPi[bin][a][b];
+          pr = fmaf(qr, ar[b], pr);
+          pr = fmaf(-qi, ai[b], pr);
+          pi = fmaf(qr, ai[b], pi);
+          pi = fmaf(qi, ar[b], pi);
+        }
+        pnr[a] = pr; pni[a] = pi;
       }
       if (tb < I) {
 #pragma unroll
-        for (int a = 0; a < I; ++a) { sPr[bin][a][c] = br[a]; sPi[bin][a][c] = bi[a]; }
+        for (int a = 0; a < I; ++a) { sPr[bin][a][c] = pnr[a]; sPi[bin][a][c] = pni[a]; }
       }
     }
     __syncthreads();
@@ -237,6 +292,26 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
   for (int t = tb; t < I * I; t += T)
     s.P[(size_t)f * I * I + t] = make_float2(sPr[bin][t / I][t % I], sPi[bin][t / I][t % I]);
   for (int t = tb; t < J * I; t += T) s.lam[(size_t)f * J * I + t] = sLam[bin][t];
+}
+
+// One problem: workgroup g owns bins g*bpw .. (the last may own fewer).
+template <int I, int J, int NPT>
+__global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_iter, int bpw) {
+  const int f0 = blockIdx.x * bpw;
+  const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
+  as_resident_body<I, J, NPT>(s, f0, nb, n_iter);
+}
+
+// Many problems of the same (I, J): workgroup g takes tile g = (problem,
+// bin) of a table the host sorts by decreasing N, so the hardware dispatcher
+// hands the longest tiles out first.
+template <int I, int J, int NPT>
+__global__ __launch_bounds__(kResMaxBlock) void k_as_resident_batch(const DevState* __restrict__ states,
+                                                                    const int2* __restrict__ tiles,
+                                                                    int n_iter) {
+  const int2 t = tiles[blockIdx.x];
+  const DevState s = states[t.x];
+  as_resident_body<I, J, NPT>(s, t.y, 1, n_iter);
 }
 
 // Frequency-resident conventional FCA EM (Section 3.3), the same execution
@@ -361,11 +436,12 @@ hipError_t launch_em_iter_resident(const DevState& s, hipStream_t st, int n_iter
   }
 }
 
-// Register budget of the resident kernel: NPT points of x (2I), v (J) and
-// the eq. 23 weights (I) per lane.
+// Register budget of the resident kernel: NPT points of y (2I), v (J), the
+// eq. 23 weights (I) and, up to I = 4, x (2I) per lane.
 template <int I, int J>
 constexpr int res_max_npt() {
-  return (16 * (3 * I + J) <= 192) ? 16 : (12 * (3 * I + J) <= 192) ? 12 : (8 * (3 * I + J) <= 192) ? 8 : 4;
+  constexpr int per = (kResXInRegs<I> ? 5 * I : 3 * I) + J;
+  return (16 * per <= 224) ? 16 : (12 * per <= 224) ? 12 : (8 * per <= 224) ? 8 : 4;
 }
 
 template <int I, int J>
@@ -374,6 +450,29 @@ int as_resident_fits(int N, int waves, int bpw) {
   if (bpw != 1 && bpw != 2) return 0;
   if (bpw == 2 && waves < 2) return 0;
   return N <= res_max_npt<I, J>() * (waves / bpw) * kWave ? 1 : 0;
+}
+
+// Batched launch: tiles of problems whose N are at most n_max, one workgroup
+// of `waves` waves per tile.
+template <int I, int J>
+hipError_t launch_as_batch_resident(const DevState* states, const int2* tiles, int ntiles, int n_max,
+                                    hipStream_t st, int n_iter, int waves) {
+  const int T = waves * kWave;
+  const int need = (n_max + T - 1) / T;
+  constexpr int mx = res_max_npt<I, J>();
+  dim3 grid(ntiles), block(T);
+  if (ntiles <= 0) return hipSuccess;
+  if (need <= 4)
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, 4>), grid, block, 0, st, states, tiles, n_iter);
+  else if (need <= 8 && mx >= 8)
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, states, tiles, n_iter);
+  else if (need <= 12 && mx >= 12)
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, states, tiles, n_iter);
+  else if (need <= 16 && mx >= 16)
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, states, tiles, n_iter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 template <int I, int J>

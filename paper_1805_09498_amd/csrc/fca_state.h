@@ -11,6 +11,10 @@ constexpr int kBlock = 256;
 constexpr int kPts = 4;
 constexpr int kChunk = kBlock * kPts;
 constexpr int kChunkEm = kBlock;  // FCA EM: one point per lane
+// Largest I whose frequency-resident FastFCA-AS kernel runs K > 1
+// fixed-point steps per iteration; larger I with K > 1 uses the streaming
+// kernels.
+constexpr int kResMaxIK = 4;
 
 // Internal layouts (library-owned):
 //   xs   [F][2I][Npad]  split-complex mixture: plane i = Re x_i, plane I+i = Im x_i
@@ -43,6 +47,8 @@ struct KernelSet {
   hipError_t (*as_iter_stream)(const DevState&, hipStream_t);
   hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves, int bpw);
   int (*as_resident_fits)(int N, int waves, int bpw);
+  hipError_t (*as_batch_resident)(const DevState* states, const int2* tiles, int ntiles, int n_max,
+                                  hipStream_t, int n_iter, int waves);
   hipError_t (*em_iter)(const DevState&, hipStream_t);
   hipError_t (*em_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
   int (*em_resident_fits)(int N, int waves);

@@ -33,7 +33,9 @@ FCA_METHOD_EM = 1
 
 EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
             "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
-            "fca_get_option", "fca_last_error", "fca_destroy")
+            "fca_get_option", "fca_last_error", "fca_destroy",
+            "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
+            "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy")
 
 
 def _load():
@@ -63,6 +65,22 @@ def _load():
     lib.fca_last_error.restype = c
     lib.fca_destroy.argtypes = [vp]
     lib.fca_destroy.restype = None
+    ip = ctypes.POINTER(ctypes.c_int)
+    pp = ctypes.POINTER(vp)
+    lib.fca_batch_init.argtypes = [pp, i, ip, ip, ip, ip, pp, pp, pp, pp, vp]
+    lib.fca_batch_init.restype = i
+    lib.fca_batch_iterate.argtypes = [vp, i]
+    lib.fca_batch_iterate.restype = i
+    lib.fca_batch_context.argtypes = [vp, i, pp]
+    lib.fca_batch_context.restype = i
+    lib.fca_batch_set_option.argtypes = [vp, c, ctypes.c_longlong]
+    lib.fca_batch_set_option.restype = i
+    lib.fca_batch_get_option.argtypes = [vp, c, i, ctypes.POINTER(ctypes.c_longlong)]
+    lib.fca_batch_get_option.restype = i
+    lib.fca_batch_last_error.argtypes = [vp]
+    lib.fca_batch_last_error.restype = c
+    lib.fca_batch_destroy.argtypes = [vp]
+    lib.fca_batch_destroy.restype = None
     return lib
 
 
@@ -106,16 +124,18 @@ def _stream_handle(stream):
 class FcaContext:
     """An opaque libfastfca context (one mixture, one method)."""
 
-    def __init__(self, handle, method, F, N, I, J, stream, keep):
+    def __init__(self, handle, method, F, N, I, J, stream, keep, owned=True):
         self.handle = handle
         self.method = method
         self.F, self.N, self.I, self.J = F, N, I, J
         self.stream = stream
         self._keep = keep   # inputs stay referenced until the stream has consumed them
+        self.owned = owned  # False for the contexts of a batch
 
     def __del__(self):
         try:
-            fca_destroy(self)
+            if self.owned:
+                fca_destroy(self)
         except Exception:
             pass
 
@@ -201,6 +221,83 @@ def fca_get_option(ctx, key):
 
 
 def fca_destroy(ctx):
+    if not ctx.owned:
+        raise ValueError("the contexts of a batch are released by fca_batch_destroy")
     if ctx.handle is not None and ctx.handle.value:
         lib.fca_destroy(ctx.handle)
     ctx.handle = ctypes.c_void_p()
+
+
+class FcaBatch:
+    """An opaque libfastfca batch of FastFCA-AS mixtures."""
+
+    def __init__(self, handle, shapes, stream, keep):
+        self.handle = handle
+        self.shapes = shapes          # [(F, N, I, J)] per mixture
+        self.stream = stream
+        self._keep = keep
+
+    def __del__(self):
+        try:
+            fca_batch_destroy(self)
+        except Exception:
+            pass
+
+
+def fca_batch_last_error(batch=None):
+    return lib.fca_batch_last_error(batch.handle if batch is not None else None).decode()
+
+
+def _bcheck(status, batch=None):
+    if status != FCA_OK:
+        raise FcaError(status, fca_batch_last_error(batch))
+
+
+def fca_batch_init(mixtures, stream=None):
+    """mixtures: sequence of (x, v0, lam0, P0) device tensors in the layouts of
+    fca_init (complex64 / float32)."""
+    n = len(mixtures)
+    Fs, Ns, Is, Js, ptrs = [], [], [], [], [[], [], [], []]
+    for k, (x, v0, lam0, P0) in enumerate(mixtures):
+        F, N, I = x.shape
+        J = v0.shape[2]
+        Fs.append(F); Ns.append(N); Is.append(I); Js.append(J)
+        for lst, t, dt, shp, nm in ((ptrs[0], x, torch.complex64, (F, N, I), "x"),
+                                    (ptrs[1], v0, torch.float32, (F, N, J), "v0"),
+                                    (ptrs[2], lam0, torch.float32, (F, J, I), "lam0"),
+                                    (ptrs[3], P0, torch.complex64, (F, I, I), "P0")):
+            lst.append(_ptr(t, dt, shp, f"mixture {k} {nm}"))
+    ia = lambda a: (ctypes.c_int * n)(*a)
+    pa = lambda a: (ctypes.c_void_p * n)(*[p.value for p in a])
+    sh, s = _stream_handle(stream)
+    h = ctypes.c_void_p()
+    _bcheck(lib.fca_batch_init(ctypes.byref(h), n, ia(Fs), ia(Ns), ia(Is), ia(Js),
+                               pa(ptrs[0]), pa(ptrs[1]), pa(ptrs[2]), pa(ptrs[3]), sh))
+    return FcaBatch(h, list(zip(Fs, Ns, Is, Js)), s, tuple(mixtures))
+
+
+def fca_batch_iterate(batch, n_iter):
+    _bcheck(lib.fca_batch_iterate(batch.handle, int(n_iter)), batch)
+
+
+def fca_batch_context(batch, m):
+    out = ctypes.c_void_p()
+    _bcheck(lib.fca_batch_context(batch.handle, int(m), ctypes.byref(out)), batch)
+    F, N, I, J = batch.shapes[m]
+    return FcaContext(out, FCA_METHOD_AS, F, N, I, J, batch.stream, (batch,), owned=False)
+
+
+def fca_batch_set_option(batch, key, value):
+    _bcheck(lib.fca_batch_set_option(batch.handle, key.encode(), int(value)), batch)
+
+
+def fca_batch_get_option(batch, key, group=0):
+    out = ctypes.c_longlong()
+    _bcheck(lib.fca_batch_get_option(batch.handle, key.encode(), int(group), ctypes.byref(out)), batch)
+    return out.value
+
+
+def fca_batch_destroy(batch):
+    if batch.handle is not None and batch.handle.value:
+        lib.fca_batch_destroy(batch.handle)
+    batch.handle = ctypes.c_void_p()

@@ -45,7 +45,9 @@ def test_header_declares_the_expected_calls():
     assert declared_functions() == sorted([
         "fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
         "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
-        "fca_get_option", "fca_last_error", "fca_destroy"])
+        "fca_get_option", "fca_last_error", "fca_destroy",
+        "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
+        "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy"])
 
 
 def test_every_declared_function_is_exported(lib):
@@ -84,6 +86,27 @@ def test_null_context_calls(lib):
     assert lib.fca_loglik(None, ctypes.byref(d)) == -1
     lib.fca_destroy(None)
     assert lib.fca_init(None, 0, 1, 1, 1, 1, FAKE, FAKE, FAKE, FAKE, None, None) == -1
+
+
+def test_batch_init_rejects_bad_arguments(lib):
+    lib.fca_batch_init.restype = ctypes.c_int
+    h = ctypes.c_void_p(5)
+    assert lib.fca_batch_init(ctypes.byref(h), 0, None, None, None, None, None, None, None, None, None) == -1
+    assert h.value is None
+    n = 2
+    ints = (ctypes.c_int * n)(4, 4)
+    bad_i = (ctypes.c_int * n)(3, 9)        # I = 9 unsupported for mixture 1
+    ptr = (ctypes.c_void_p * n)(FAKE, FAKE)
+    st = lib.fca_batch_init(ctypes.byref(h), n, ints, (ctypes.c_int * n)(2, 2), (ctypes.c_int * n)(3, 3), ints,
+                            ptr, ptr, ptr, ptr, None)
+    assert st == -1   # N = 2 < I = 3 for mixture 0: rejected before any device work
+    lib.fca_batch_last_error.restype = ctypes.c_char_p
+    lib.fca_batch_last_error.argtypes = [ctypes.c_void_p]
+    assert b"mixture 0" in lib.fca_batch_last_error(None)
+    st = lib.fca_batch_init(ctypes.byref(h), n, ints, (ctypes.c_int * n)(8, 8), bad_i, ints,
+                            ptr, ptr, ptr, ptr, None)
+    assert st == -2   # I = 9 in mixture 1: every mixture is checked before any device work
+    assert b"mixture 1" in lib.fca_batch_last_error(None)
 
 
 def test_binding_has_no_fallback():

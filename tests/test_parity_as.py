@@ -74,6 +74,36 @@ def test_inner_fixed_point_steps(ff):
         assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM
 
 
+@pytest.mark.parametrize("I,J", [(4, 3), (6, 4)])
+def test_inner_fixed_point_steps_larger_I(ff, I, J):
+    """K = 3 at I = 4 (resident and streaming kernels) and I = 6 (streaming
+    only: the automatic path picks it, forcing the resident one is refused)."""
+    p = problem(I, J, 9, 70, seed=6)
+    v_ref, lam_ref, P_ref = oracle_as(p, 1, K=3)
+    for path in ((0, 1, 2) if I <= 4 else (0, 2)):
+        ctx = run_as(ff, p, 1, path=path, K=3)
+        v, lam, P = params(ff, ctx)
+        assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM, path
+    if I > 4:
+        with pytest.raises(ff.FcaError):
+            run_as(ff, p, 1, path=1, K=3)
+
+
+@pytest.mark.parametrize("I,J,N", [(3, 2, 617), (6, 7, 1200)])
+def test_ill_conditioned_low_bins_over_iterations(ff, I, J, N):
+    """Plane waves in a diffuse field on a uniform array: near DC the weighted
+    covariances of eq. 23 reach condition numbers of 1e3 - 1e4.  Parameters
+    after 1, 2 and 3 iterations against the oracle, every bin."""
+    p = problem(I, J, 9, N, seed=17, spatial="ula")
+    ctx = run_as(ff, p, 0)
+    v_ref, lam_ref, P_ref = p.v0, p.lam0, p.P0
+    for it in range(3):
+        ff.fastfca_as_iterate(ctx, 1)
+        v_ref, lam_ref, P_ref = oracle.fastfca_as_step(p.x, v_ref, lam_ref, P_ref)
+        v, lam, P = params(ff, ctx)
+        assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM, it
+
+
 def test_wiener_sums_to_mixture_and_matches_oracle(ff):
     p = problem(**SMALL)
     ctx = run_as(ff, p, 3)
