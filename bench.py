@@ -64,9 +64,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_as_resident_speech10s_traffic.t
 
 def profiled_traffic(workload, shape):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
-    changed since the counters were taken (source hash), or the workload or
-    launch shape differ from the profiled ones."""
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (one value per launch shape), or
+    None when the kernel sources changed since the counters were taken
+    (source hash), or the workload or launch shape was not profiled."""
     import hashlib
     try:
         fields = dict(line.split(": ", 1) for line in open(TRAFFIC_FILE).read().splitlines()
@@ -76,11 +76,11 @@ def profiled_traffic(workload, shape):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_1805_09498_amd", "csrc", f), "rb").read())
-    want_shape = f"waves={shape['waves_per_workgroup']} bins_per_wg={shape['bins_per_workgroup']}"
-    if (fields.get("source_sha256") != h.hexdigest() or fields.get("workload") != workload
-            or fields.get("launch_shape") != want_shape):
+    key = (f"traffic_bytes_per_launch[waves={shape['waves_per_workgroup']} "
+           f"bins_per_wg={shape['bins_per_workgroup']}]")
+    if fields.get("source_sha256") != h.hexdigest() or fields.get("workload") != workload or key not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[key])
 
 
 def parse():
@@ -117,7 +117,7 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "launches": 5}))
 
 
-def cpu_baseline(prob, iters_as=30, iters_em=5):
+def cpu_baseline(prob, iters_as=60, iters_em=8):
     """The FP64 oracle as it stands, single-threaded, on the same rounded
     inputs: a bounded number of iterations of each method."""
     import oracle
