@@ -103,6 +103,9 @@ def parse():
     ap.add_argument("--batch", action="store_true",
                     help="uneven batch workload instead (64 mixtures, F=513, 30 iterations per step)")
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--no-fwd-bwd", action="store_true", help="skip the forward + reverse pass leg")
+    ap.add_argument("--fwd-bwd-iters", type=int, default=20)
+    ap.add_argument("--ckpt-every", type=int, default=5)
     return ap.parse_args()
 
 
@@ -202,6 +205,49 @@ def batch_main(args):
                                f"{iters} iterations per step (parameters reset each step)",
                    "graph": bool(args.graph)},
         "achieved_TFLOPs": flops / (it_ms * 1e-3) / 1e12, "groups": groups}))
+
+
+def fwd_bwd_leg(ff, x, v0, lam0, P0, n_iter, every, steps, warmup):
+    """Recorded forward (n_iter iterations, a checkpoint every `every`, Wiener
+    filter) and the full reverse pass for a fixed seeded dL/d(images), from the
+    same initial point each step.  Times per step and per half (HIP events on
+    the current stream, the library's stream here)."""
+    import torch
+    F, N, I = x.shape
+    J = v0.shape[2]
+    g = torch.randn((J, F, N, I), dtype=torch.complex64, device=x.device,
+                    generator=torch.Generator(device=x.device).manual_seed(0))
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, x, v0, lam0, P0)
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def step(record):
+        ff.fca_set_params(ctx, v0, lam0, P0)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        ff.fastfca_as_forward(ctx, n_iter, every)
+        e1.record(stream)
+        ff.fastfca_as_backward(ctx, g)
+        e2.record(stream)
+        if record:
+            ev.append((e0, e1, e2))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    fwd = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    bwd = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    ff.fca_destroy(ctx)
+    return {"workload": f"I={I}, J={J}, F={F}, N={N}: {n_iter} recorded FastFCA-AS iterations + Wiener "
+                        f"filter, then the reverse pass (hand-written adjoints, checkpoint every {every}) "
+                        "for a fixed dL/d(images) to x, v0, lambda0, P0",
+            "value": N * F * n_iter / (ms * 1e-3), "unit": "TF-point-iters/s (forward + backward)",
+            "ms_per_step": ms, "forward_ms": fwd, "backward_ms": bwd}
 
 
 def main():
@@ -323,6 +369,9 @@ def main():
                          "launch_shape": shape_em,
                          "achieved_TFLOPs": fca_em_flops_per_point_iter(I, J) * pts / (it_ms_em * 1e-3) / 1e12}
         res["speedup_vs_fca_em"] = value / v_em
+    if not args.no_fwd_bwd:
+        res["fwd_bwd"] = fwd_bwd_leg(ff, x, v0, lam0, P0, args.fwd_bwd_iters, args.ckpt_every,
+                                     max(3, args.steps // 4), 2)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(res))

@@ -204,6 +204,38 @@ const char *fca_batch_last_error(const fca_batch *b);
 /* Synchronise the stream and release the batch and its contexts. */
 void fca_batch_destroy(fca_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Derivatives of the unrolled method (reverse mode): a recorded run of
+ * hybrid iterations (Section 4.4) followed by the Wiener filter (eq. 3 with
+ * eq. 15), and the derivative of a real loss on its output with respect to
+ * the mixture and the starting parameters.
+ * ------------------------------------------------------------------------ */
+
+/* Run n_iter hybrid iterations (K = 1) from the context's current state, as
+ * fastfca_as_iterate does, recording the state every ckpt_every iterations,
+ * then write the Wiener estimates of the final state into out [J][F][N][I]
+ * (device, may be NULL).  The recording lives in library-owned device memory
+ * (ceil(n_iter / ckpt_every) + ckpt_every + 1 copies of (v, lambda, P), plus
+ * the adjoint buffers) until the next call of this function or
+ * fca_destroy.  n_iter >= 0, ckpt_every >= 1.  FCA_ERR_UNSUPPORTED when the
+ * "K" option is not 1.  Asynchronous (a context's first iterations may run
+ * the launch-shape tuner, see "autotune"). */
+fca_status fastfca_as_forward(fca_ctx *ctx, int n_iter, int ckpt_every, fca_c64 *out);
+
+/* Reverse-mode derivative of the last fastfca_as_forward of ctx.  grad_out
+ * [J][F][N][I] is dL/d(out) for a real loss L; the call writes dL/dx
+ * [F][N][I], dL/dv0 [F][N][J], dL/dlam0 [F][J][I] and dL/dP0 [F][I][I],
+ * where x is the context's mixture and (v0, lam0, P0) the state the recorded
+ * run started from.  A complex entry z receives dL/dRe z + i dL/dIm z (the
+ * convention of PyTorch's autograd).  All pointers are device pointers; any
+ * output may be NULL.  The iterations of each checkpoint segment are rebuilt
+ * with the recorded launch shape (bitwise the recorded states) and their
+ * adjoints run in reverse order.  FCA_ERR_STATE if the state changed since
+ * the recorded run (an iterate or set_params call).  The call may be
+ * repeated with other grad_out.  Asynchronous. */
+fca_status fastfca_as_backward(fca_ctx *ctx, const fca_c64 *grad_out, fca_c64 *grad_x, float *grad_v0,
+                               float *grad_lam0, fca_c64 *grad_P0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,509 @@
+// Reverse-mode derivatives (adjoints) of FastFCA-AS: one hybrid iteration
+// (Section 4.4: eq. 15-20, then eq. 23) and the multichannel Wiener filter
+// (eq. 3 with eq. 15).  Given dL/d(outputs) they produce dL/d(inputs) for a
+// real loss L; a complex quantity z carries dL/dRe z + i dL/dIm z.
+//
+// One workgroup per frequency bin; the lanes stride over the bin's frames.
+// The sums over n of the forward step become broadcasts here and the
+// per-frame contributions to per-bin adjoints (lambda, P) are block sums.
+//
+// Iteration (forward in the basis of y = P^H x, A = P^-1 P_new):
+//   q = v lambda, d = sum_j q, g = q / d, r = g^2 |y|^2 + q (1 - g)
+//   v' = (1/I) sum_i r / lambda             lambda' = (1/N) sum_n r / v'
+//   w = 1 / (sum_j v' lambda')              S_i = sum_n w_i y y^H
+//   S_i a_i = N e_i                         P_new = P A
+// Adjoint, with b_i = S_i^-1 (P^H Pbar_new)_i, alpha_i = a_i^H y,
+// beta_i = b_i^H y:
+//   Pbar = Pbar_new A^H + sum_n x ybar^H,   xbar = P ybar
+//   wbar_i = -Re(conj(beta_i) alpha_i),     d'bar = -wbar w^2
+//   lambda'bar += sum_n d'bar v',  v'bar += d'bar lambda' - (lambda'bar r) / (N v'^2)
+//   rbar = lambda'bar / (N v') + v'bar / (I lambda)
+//   ybar = -sum_i w_i (b_i alpha_i + a_i beta_i) + 2 (sum_j rbar dr/d|y|^2) y
+// and the chain through r(q, d, |y|^2), q = v lambda, d = sum_j q.
+#pragma once
+
+#include "fca_kernels.h"
+
+namespace fca {
+
+constexpr int kAdjBlock = 256;
+
+template <int I, int J>
+constexpr int adj_red_size() {
+  constexpr int a = pad4((I * I * I <= 64) ? I * I * I : I * I);
+  constexpr int b = pad4(J * I + 2 * I * I);
+  return (a > b ? a : b) * (kAdjBlock / kWave);
+}
+
+// Block sum of V per-lane values into out[V] (LDS or global): transposed wave
+// sums, then the sum over the block's waves.  red holds
+// pad4(V) * (waves per block) floats.  Ends with a barrier.
+template <int V>
+__device__ inline void block_sum_t(const float (&a)[V], float* out, float* red) {
+  constexpr int S = pad4(V);
+  wave_totals_to_lds<V>(a, red, S);
+  __syncthreads();
+  const int nw = blockDim.x / kWave;
+  for (int k = threadIdx.x; k < V; k += blockDim.x) {
+    float t = 0.f;
+    for (int w = 0; w < nw; ++w) t += red[w * S + k];
+    out[k] = t;
+  }
+  __syncthreads();
+}
+
+// The bin's x at frame n (split planes) and y = P^H x.
+template <int I>
+__device__ __forceinline__ void adj_load_x(const float* xf, int Npad, int n, float (&xr)[I], float (&xi)[I]) {
+#pragma unroll
+  for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * Npad + n]; xi[i] = xf[(size_t)(I + i) * Npad + n]; }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint of one hybrid iteration (K = 1).
+// ----------------------------------------------------------------------------
+template <int I, int J>
+__global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
+  constexpr bool kOne = I * I * I <= 64;
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int N = s.N, Np = s.Npad;
+  __shared__ float sPr[I][I], sPi[I][I];    // P_t
+  __shared__ float sQr[I][I], sQi[I][I];    // Pbar of P_{t+1}
+  __shared__ float sAr[I][I], sAi[I][I];    // column i: a_i
+  __shared__ float sBr[I][I], sBi[I][I];    // column i: b_i
+  __shared__ float sLt[J * I], sLn[J * I], sLb[J * I];
+  __shared__ float sS[I][I * I];            // S_i, packed Hermitian
+  __shared__ float sOut[J * I + 2 * I * I];
+  __shared__ float red[adj_red_size<I, J>()];
+
+  for (int t = tid; t < I * I; t += kAdjBlock) {
+    const float2 p = a.P_t[(size_t)f * I * I + t], q = a.Pb_in[(size_t)f * I * I + t];
+    sPr[t / I][t % I] = p.x; sPi[t / I][t % I] = p.y;
+    sQr[t / I][t % I] = q.x; sQi[t / I][t % I] = q.y;
+  }
+  for (int t = tid; t < J * I; t += kAdjBlock) {
+    sLt[t] = a.lam_t[(size_t)f * J * I + t];
+    sLn[t] = a.lam_n[(size_t)f * J * I + t];
+  }
+  __syncthreads();
+  float Pr[I][I], Pi[I][I], lt[J][I], ln[J][I];
+#pragma unroll
+  for (int r = 0; r < I; ++r)
+#pragma unroll
+    for (int c = 0; c < I; ++c) { Pr[r][c] = sPr[r][c]; Pi[r][c] = sPi[r][c]; }
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) { lt[j][i] = sLt[j * I + i]; ln[j][i] = sLn[j * I + i]; }
+
+  const float* xf = s.xs + (size_t)f * 2 * I * Np;
+  const float* vt = a.v_t + (size_t)f * J * Np;
+  const float* vn = a.v_n + (size_t)f * J * Np;
+  const float* vbi = a.vb_in + (size_t)f * J * Np;
+  float* vbo = a.vb_out + (size_t)f * J * Np;
+  float* xb = a.xb + (size_t)f * 2 * I * Np;
+
+  // new weights w_i = 1 / sum_j v'_j lambda'_ji at frame n
+  auto weights = [&](int n, float (&vN)[J], float (&w)[I]) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) vN[j] = vn[(size_t)j * Np + n];
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      float d = 0.f;
+#pragma unroll
+      for (int j = 0; j < J; ++j) d = fmaf(vN[j], ln[j][i], d);
+      w[i] = rcp(d);
+    }
+  };
+
+  // ---- pass 0: S_i = sum_n w_i y y^H (recorded by the forward run, or
+  // summed again here) ------------------------------------------------------
+  if (a.S_t) {
+    for (int t = tid; t < I * I * I; t += kAdjBlock) (&sS[0][0])[t] = a.S_t[(size_t)f * I * I * I + t];
+    __syncthreads();
+  } else if constexpr (kOne) {
+    float acc[I * I * I];
+#pragma unroll
+    for (int k = 0; k < I * I * I; ++k) acc[k] = 0.f;
+    for (int n = tid; n < N; n += kAdjBlock) {
+      float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], z[I * I];
+      adj_load_x<I>(xf, Np, n, xr, xi);
+      as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+      weights(n, vN, w);
+      herm_outer<I>(z, yr, yi);
+#pragma unroll
+      for (int i = 0; i < I; ++i)
+#pragma unroll
+        for (int k = 0; k < I * I; ++k) acc[i * I * I + k] = fmaf(w[i], z[k], acc[i * I * I + k]);
+    }
+    block_sum_t<I * I * I>(acc, &sS[0][0], red);
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < I; ++i) {
+      float acc[I * I];
+#pragma unroll
+      for (int k = 0; k < I * I; ++k) acc[k] = 0.f;
+      for (int n = tid; n < N; n += kAdjBlock) {
+        float xr[I], xi[I], yr[I], yi[I], vN[J], w[I];
+        adj_load_x<I>(xf, Np, n, xr, xi);
+        as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+        weights(n, vN, w);
+        float wi = w[0];
+#pragma unroll
+        for (int k = 1; k < I; ++k) wi = (k == i) ? w[k] : wi;
+        herm_rank1_acc<I>(acc, wi, yr, yi);
+      }
+      block_sum_t<I * I>(acc, &sS[i][0], red);
+    }
+  }
+
+  // ---- per bin: a_c = N S_c^-1 e_c and b_c = S_c^-1 (P^H Pbar_new)_c ------
+  if (tid < I) {
+    const int c = tid;
+    float Sr[I][I], Si[I][I];
+#pragma unroll
+    for (int r = 0; r < I; ++r)
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        Sr[r][k] = sS[c][r * I + k];
+        Si[r][k] = (k > r) ? sS[c][k * I + r] : 0.f;
+      }
+    float ar[I], ai[I], br[I], bi[I];
+#pragma unroll
+    for (int r = 0; r < I; ++r) {
+      ar[r] = (r == c) ? float(N) : 0.f; ai[r] = 0.f;
+      // (P^H Pbar_new)_rc = sum_k conj(P_kr) Pbar_kc
+      float tr = 0.f, ti = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        const float qr = sQr[k][c], qi = sQi[k][c];
+        tr = fmaf(Pr[k][r], qr, fmaf(Pi[k][r], qi, tr));
+        ti = fmaf(Pr[k][r], qi, fmaf(-Pi[k][r], qr, ti));
+      }
+      br[r] = tr; bi[r] = ti;
+    }
+    herm_solve<I>(Sr, Si, ar, ai);
+    herm_solve<I>(Sr, Si, br, bi);
+#pragma unroll
+    for (int r = 0; r < I; ++r) { sAr[r][c] = ar[r]; sAi[r][c] = ai[r]; sBr[r][c] = br[r]; sBi[r][c] = bi[r]; }
+  }
+  __syncthreads();
+  float Ar[I][I], Ai[I][I], Br[I][I], Bi[I][I];
+#pragma unroll
+  for (int r = 0; r < I; ++r)
+#pragma unroll
+    for (int c = 0; c < I; ++c) { Ar[r][c] = sAr[r][c]; Ai[r][c] = sAi[r][c]; Br[r][c] = sBr[r][c]; Bi[r][c] = sBi[r][c]; }
+
+  // d'bar_i at frame n, with alpha_i = a_i^H y and beta_i = b_i^H y
+  auto dprime_bar = [&](const float (&yr)[I], const float (&yi)[I], const float (&w)[I], float (&alr)[I],
+                        float (&ali)[I], float (&ber)[I], float (&bei)[I], float (&dpb)[I]) {
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        a0 = fmaf(Ar[k][i], yr[k], fmaf(Ai[k][i], yi[k], a0));
+        a1 = fmaf(Ar[k][i], yi[k], fmaf(-Ai[k][i], yr[k], a1));
+        b0 = fmaf(Br[k][i], yr[k], fmaf(Bi[k][i], yi[k], b0));
+        b1 = fmaf(Br[k][i], yi[k], fmaf(-Bi[k][i], yr[k], b1));
+      }
+      alr[i] = a0; ali[i] = a1; ber[i] = b0; bei[i] = b1;
+      const float wbar = -fmaf(b0, a0, b1 * a1);  // -Re(conj(beta) alpha)
+      dpb[i] = -wbar * w[i] * w[i];
+    }
+  };
+
+  // ---- pass 1: lambda'bar total = lambda'bar_in + sum_n d'bar v' ----------
+  {
+    float acc[J * I];
+#pragma unroll
+    for (int k = 0; k < J * I; ++k) acc[k] = 0.f;
+    for (int n = tid; n < N; n += kAdjBlock) {
+      float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I];
+      adj_load_x<I>(xf, Np, n, xr, xi);
+      as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+      weights(n, vN, w);
+      dprime_bar(yr, yi, w, alr, ali, ber, bei, dpb);
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int i = 0; i < I; ++i) acc[j * I + i] = fmaf(dpb[i], vN[j], acc[j * I + i]);
+    }
+    block_sum_t<J * I>(acc, sLb, red);
+    for (int t = tid; t < J * I; t += kAdjBlock) sLb[t] += a.lb_in[(size_t)f * J * I + t];
+    __syncthreads();
+  }
+  float lb[J][I];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) lb[j][i] = sLb[j * I + i];
+
+  // ---- pass 2: everything else ----------------------------------------------
+  const float invN = 1.0f / float(N), invI = 1.0f / float(I);
+  float il[J][I];  // 1 / lambda_t
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) il[j][i] = rcp(lt[j][i]);
+  float acc[J * I + 2 * I * I];  // lambda-bar sums, then sum_n x ybar^H (re, im)
+#pragma unroll
+  for (int k = 0; k < J * I + 2 * I * I; ++k) acc[k] = 0.f;
+  for (int n = tid; n < N; n += kAdjBlock) {
+    float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I], v[J], vb[J];
+    adj_load_x<I>(xf, Np, n, xr, xi);
+    as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+    weights(n, vN, w);
+    dprime_bar(yr, yi, w, alr, ali, ber, bei, dpb);
+#pragma unroll
+    for (int j = 0; j < J; ++j) { v[j] = vt[(size_t)j * Np + n]; vb[j] = vbi[(size_t)j * Np + n]; }
+    float id[I], e[I];  // 1 / d_i, |y_i|^2
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      float t = 0.f;
+#pragma unroll
+      for (int j = 0; j < J; ++j) t = fmaf(v[j], lt[j][i], t);
+      id[i] = rcp(t);
+      e[i] = fmaf(yr[i], yr[i], yi[i] * yi[i]);
+    }
+    // v'bar total and the rbar of every (j, i)
+    float db2[I], eb[I], vbar[J];
+#pragma unroll
+    for (int i = 0; i < I; ++i) { db2[i] = 0.f; eb[i] = 0.f; }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const float ivn = rcp(vN[j]);
+      float vbt = vb[j], rl = 0.f;
+      float r[I], g[I];
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        vbt = fmaf(dpb[i], ln[j][i], vbt);
+        const float q = v[j] * lt[j][i];
+        g[i] = q * id[i];
+        r[i] = fmaf(g[i] * g[i], e[i], q * (1.f - g[i]));
+        rl = fmaf(lb[j][i], r[i], rl);
+      }
+      vbt -= rl * invN * ivn * ivn;
+      float vj = 0.f;
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const float rbar = fmaf(lb[j][i], invN * ivn, vbt * invI * il[j][i]);
+        acc[j * I + i] = fmaf(-vbt * r[i] * invI, il[j][i] * il[j][i], acc[j * I + i]);
+        const float gi = g[i];
+        const float dq = fmaf(2.f * gi * id[i], e[i], 1.f - 2.f * gi);   // dr/dq
+        const float dd = gi * gi * fmaf(-2.f * e[i], id[i], 1.f);        // dr/dd
+        const float qbar = rbar * dq;
+        db2[i] = fmaf(rbar, dd, db2[i]);
+        eb[i] = fmaf(rbar, gi * gi, eb[i]);                         // dr/d|y|^2 = g^2
+        vj = fmaf(qbar, lt[j][i], vj);
+        acc[j * I + i] = fmaf(qbar, v[j], acc[j * I + i]);
+      }
+      vbar[j] = vj;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        vbar[j] = fmaf(db2[i], lt[j][i], vbar[j]);
+        acc[j * I + i] = fmaf(db2[i], v[j], acc[j * I + i]);
+      }
+      vbo[(size_t)j * Np + n] = vbar[j];
+    }
+    // ybar = -sum_i w_i (b_i alpha_i + a_i beta_i) + 2 eb y
+    float ybr[I], ybi[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      float tr = 2.f * eb[k] * yr[k], ti = 2.f * eb[k] * yi[k];
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        // b_ki alpha_i + a_ki beta_i
+        const float ur = (Br[k][i] * alr[i] - Bi[k][i] * ali[i]) + (Ar[k][i] * ber[i] - Ai[k][i] * bei[i]);
+        const float ui = (Br[k][i] * ali[i] + Bi[k][i] * alr[i]) + (Ar[k][i] * bei[i] + Ai[k][i] * ber[i]);
+        tr = fmaf(-w[i], ur, tr);
+        ti = fmaf(-w[i], ui, ti);
+      }
+      ybr[k] = tr; ybi[k] = ti;
+    }
+    // xbar += P ybar;  sum_n x ybar^H
+#pragma unroll
+    for (int r = 0; r < I; ++r) {
+      float tr = 0.f, ti = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        tr = fmaf(Pr[r][k], ybr[k], fmaf(-Pi[r][k], ybi[k], tr));
+        ti = fmaf(Pr[r][k], ybi[k], fmaf(Pi[r][k], ybr[k], ti));
+      }
+      xb[(size_t)r * Np + n] += tr;
+      xb[(size_t)(I + r) * Np + n] += ti;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        // x_r conj(ybar_k)
+        acc[J * I + r * I + k] = fmaf(xr[r], ybr[k], fmaf(xi[r], ybi[k], acc[J * I + r * I + k]));
+        acc[J * I + I * I + r * I + k] = fmaf(xi[r], ybr[k], fmaf(-xr[r], ybi[k], acc[J * I + I * I + r * I + k]));
+      }
+    }
+  }
+  block_sum_t<J * I + 2 * I * I>(acc, sOut, red);
+  for (int t = tid; t < J * I; t += kAdjBlock) a.lb_out[(size_t)f * J * I + t] = sOut[t];
+  for (int t = tid; t < I * I; t += kAdjBlock) {
+    const int r = t / I, c = t % I;
+    // (Pbar_new A^H)_rc = sum_k Pbar_rk conj(A_ck)
+    float tr = sOut[J * I + t], ti = sOut[J * I + I * I + t];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      tr = fmaf(sQr[r][k], sAr[c][k], fmaf(sQi[r][k], sAi[c][k], tr));
+      ti = fmaf(sQi[r][k], sAr[c][k], fmaf(-sQr[r][k], sAi[c][k], ti));
+    }
+    a.Pb_out[(size_t)f * I * I + t] = make_float2(tr, ti);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint of the Wiener filter s_j = P^-H (g_j o y), g_ji = v_j lambda_ji / d_i
+// (needs B = P^-H in s.Bm).  gout [J][F][N][I]; writes vb_out, lb_out, Pb_out
+// and initialises xb.
+// ----------------------------------------------------------------------------
+template <int I, int J>
+__global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const float2* __restrict__ gout, AdjIter a) {
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int N = s.N, Np = s.Npad, F = s.F;
+  __shared__ float sPr[I][I], sPi[I][I], sBr[I][I], sBi[I][I];
+  __shared__ float sL[J * I];
+  __shared__ float sOut[J * I + 4 * I * I];
+  __shared__ float red[pad4(J * I + 4 * I * I) * (kAdjBlock / kWave)];
+  for (int t = tid; t < I * I; t += kAdjBlock) {
+    const float2 p = s.P[(size_t)f * I * I + t], b = s.Bm[(size_t)f * I * I + t];
+    sPr[t / I][t % I] = p.x; sPi[t / I][t % I] = p.y;
+    sBr[t / I][t % I] = b.x; sBi[t / I][t % I] = b.y;
+  }
+  for (int t = tid; t < J * I; t += kAdjBlock) sL[t] = s.lam[(size_t)f * J * I + t];
+  __syncthreads();
+  float Pr[I][I], Pi[I][I], Br[I][I], Bi[I][I], lam[J][I];
+#pragma unroll
+  for (int r = 0; r < I; ++r)
+#pragma unroll
+    for (int c = 0; c < I; ++c) { Pr[r][c] = sPr[r][c]; Pi[r][c] = sPi[r][c]; Br[r][c] = sBr[r][c]; Bi[r][c] = sBi[r][c]; }
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i < I; ++i) lam[j][i] = sL[j * I + i];
+  const float* xf = s.xs + (size_t)f * 2 * I * Np;
+  const float* vf = s.vs + (size_t)f * J * Np;
+  float* vbo = a.vb_out + (size_t)f * J * Np;
+  float* xb = a.xb + (size_t)f * 2 * I * Np;
+  // lambda-bar sums, sum_n sum_j sbar_j z_j^H (re, im), sum_n x ybar^H (re, im)
+  float acc[J * I + 4 * I * I];
+#pragma unroll
+  for (int k = 0; k < J * I + 4 * I * I; ++k) acc[k] = 0.f;
+  for (int n = tid; n < N; n += kAdjBlock) {
+    float xr[I], xi[I], yr[I], yi[I], v[J], d[I];
+    adj_load_x<I>(xf, Np, n, xr, xi);
+    as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+#pragma unroll
+    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * Np + n];
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      float t = 0.f;
+#pragma unroll
+      for (int j = 0; j < J; ++j) t = fmaf(v[j], lam[j][i], t);
+      d[i] = t;
+    }
+    float ybr[I], ybi[I], dbar[I], id[I];
+#pragma unroll
+    for (int i = 0; i < I; ++i) { ybr[i] = 0.f; ybi[i] = 0.f; dbar[i] = 0.f; id[i] = rcp(d[i]); }
+    float qb[J][I];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float sr[I], si[I];
+      const float2* gp = gout + (((size_t)j * F + f) * N + n) * I;
+#pragma unroll
+      for (int i = 0; i < I; ++i) { const float2 t = gp[i]; sr[i] = t.x; si[i] = t.y; }
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const float q = v[j] * lam[j][i], g = q * id[i];
+        // zbar_i = (B^H sbar)_i = sum_k conj(B_ki) sbar_k
+        float zr = 0.f, zi = 0.f;
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+          zr = fmaf(Br[k][i], sr[k], fmaf(Bi[k][i], si[k], zr));
+          zi = fmaf(Br[k][i], si[k], fmaf(-Bi[k][i], sr[k], zi));
+        }
+        const float gbar = fmaf(yr[i], zr, yi[i] * zi);   // Re(conj(y) zbar)
+        ybr[i] = fmaf(g, zr, ybr[i]);
+        ybi[i] = fmaf(g, zi, ybi[i]);
+        qb[j][i] = gbar * id[i];
+        dbar[i] = fmaf(-gbar * q, id[i] * id[i], dbar[i]);
+        // sbar_k conj(z_i), z_i = g y_i
+        const float zzr = g * yr[i], zzi = g * yi[i];
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+          acc[J * I + k * I + i] = fmaf(sr[k], zzr, fmaf(si[k], zzi, acc[J * I + k * I + i]));
+          acc[J * I + I * I + k * I + i] = fmaf(si[k], zzr, fmaf(-sr[k], zzi, acc[J * I + I * I + k * I + i]));
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      float vb = 0.f;
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const float t = qb[j][i] + dbar[i];
+        vb = fmaf(t, lam[j][i], vb);
+        acc[j * I + i] = fmaf(t, v[j], acc[j * I + i]);
+      }
+      vbo[(size_t)j * Np + n] = vb;
+    }
+#pragma unroll
+    for (int r = 0; r < I; ++r) {
+      float tr = 0.f, ti = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        tr = fmaf(Pr[r][k], ybr[k], fmaf(-Pi[r][k], ybi[k], tr));
+        ti = fmaf(Pr[r][k], ybi[k], fmaf(Pi[r][k], ybr[k], ti));
+      }
+      xb[(size_t)r * Np + n] = tr;
+      xb[(size_t)(I + r) * Np + n] = ti;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        acc[J * I + 2 * I * I + r * I + k] = fmaf(xr[r], ybr[k], fmaf(xi[r], ybi[k], acc[J * I + 2 * I * I + r * I + k]));
+        acc[J * I + 3 * I * I + r * I + k] = fmaf(xi[r], ybr[k], fmaf(-xr[r], ybi[k], acc[J * I + 3 * I * I + r * I + k]));
+      }
+    }
+  }
+  block_sum_t<J * I + 4 * I * I>(acc, sOut, red);
+  for (int t = tid; t < J * I; t += kAdjBlock) a.lb_out[(size_t)f * J * I + t] = sOut[t];
+  for (int t = tid; t < I * I; t += kAdjBlock) {
+    const int r = t / I, c = t % I;
+    // -(B Bbar^H B)_rc + (sum_n x ybar^H)_rc
+    float tr = sOut[J * I + 2 * I * I + t], ti = sOut[J * I + 3 * I * I + t];
+#pragma unroll
+    for (int l = 0; l < I; ++l) {
+      // (B Bbar^H)_rl = sum_k B_rk conj(Bbar_lk)
+      float mr = 0.f, mi = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        const float br = sOut[J * I + l * I + k], bi = sOut[J * I + I * I + l * I + k];
+        mr = fmaf(sBr[r][k], br, fmaf(sBi[r][k], bi, mr));
+        mi = fmaf(sBi[r][k], br, fmaf(-sBr[r][k], bi, mi));
+      }
+      tr -= mr * sBr[l][c] - mi * sBi[l][c];
+      ti -= mr * sBi[l][c] + mi * sBr[l][c];
+    }
+    a.Pb_out[(size_t)f * I * I + t] = make_float2(tr, ti);
+  }
+}
+
+template <int I, int J>
+hipError_t launch_adj_iter(const DevState& s, const AdjIter& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_adj_iter<I, J>), dim3(s.F), dim3(kAdjBlock), 0, st, s, a);
+  return hipGetLastError();
+}
+
+template <int I, int J>
+hipError_t launch_adj_wiener(const DevState& s, const float2* gout, const AdjIter& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_p_inv_herm<I>), dim3((s.F * I + 63) / 64), dim3(64), 0, st, s);
+  hipLaunchKernelGGL((k_adj_wiener<I, J>), dim3(s.F), dim3(kAdjBlock), 0, st, s, gout, a);
+  return hipGetLastError();
+}
+
+}  // namespace fca

@@ -268,6 +268,40 @@ fca_status post_check(fca_ctx* c) {
 namespace fca {
 hipError_t copy_state(fca_ctx* c, bool save) { return ::copy_state(c, save); }
 
+fca_status ctx_fail(fca_ctx* c, fca_status st, const std::string& msg) { return fail(c, st, msg); }
+fca_status ctx_hip_fail(fca_ctx* c, hipError_t e, const char* where) { return hip_fail(c, e, where); }
+
+fca_status as_iterate_chosen(fca_ctx* c, int n_iter, int* waves, int* bpw) {
+  Shape sh;
+  fca_status st = choose_shape(c, n_iter, &sh);
+  if (st != FCA_OK) return st;
+  c->last_waves = sh.waves; c->last_bpw = sh.bpw;
+  *waves = sh.waves; *bpw = sh.bpw;
+  ++c->version;
+  hipError_t e = launch_shape(c, sh, n_iter);
+  if (e != hipSuccess) return hip_fail(c, e, "FastFCA-AS iteration");
+  return FCA_OK;
+}
+
+hipError_t as_iterate_view(fca_ctx* c, const DevState& s, int waves, int bpw, int n_iter) {
+  if (waves == 0) {
+    for (int it = 0; it < n_iter; ++it) {
+      hipError_t e = c->ks->as_iter_stream(s, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  for (int done = 0; done < n_iter;) {
+    const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
+    hipError_t e = c->ks->as_iter_resident(s, c->stream, step, waves, bpw);
+    if (e != hipSuccess) return e;
+    done += step;
+  }
+  return hipSuccess;
+}
+
+fca_status post_iterate(fca_ctx* c) { return post_check(c); }
+
 fca_status validate_init(fca_method method, int F, int N, int I, int J, const void* x, const void* v0,
                          const void* lam0, const void* P0, const void* R0, std::string* msg) {
   auto bad = [&](fca_status st, const char* m) { *msg = m; return st; };
@@ -308,6 +342,8 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
   c->backup = nullptr; c->arena = nullptr; c->last_waves = -1; c->last_bpw = -1;
+  c->version = 0; c->tape = nullptr; c->tape_bytes = 0; c->tape_iters = 0; c->tape_every = 0;
+  c->tape_waves = 0; c->tape_bpw = 0; c->tape_version = ~0ULL;
 
   DevState& s = c->s;
   s.F = F; s.N = N; s.Npad = (int)Npad; s.K = 1;
@@ -388,12 +424,9 @@ fca_status fastfca_as_iterate(fca_ctx* c, int n_iter) {
   if (c->method != FCA_METHOD_AS) return fail(c, FCA_ERR_STATE, "fastfca_as_iterate on an FCA EM context");
   if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
   if (n_iter == 0) return FCA_OK;
-  Shape sh;
-  fca_status st = choose_shape(c, n_iter, &sh);
+  int w = 0, b = 0;
+  fca_status st = fca::as_iterate_chosen(c, n_iter, &w, &b);
   if (st != FCA_OK) return st;
-  c->last_waves = sh.waves; c->last_bpw = sh.bpw;
-  hipError_t e = launch_shape(c, sh, n_iter);
-  if (e != hipSuccess) return hip_fail(c, e, "FastFCA-AS iteration");
   return post_check(c);
 }
 
@@ -406,6 +439,7 @@ fca_status fca_em_iterate(fca_ctx* c, int n_iter) {
   fca_status st = choose_shape(c, n_iter, &sh);
   if (st != FCA_OK) return st;
   c->last_waves = sh.waves; c->last_bpw = sh.bpw;
+  ++c->version;
   hipError_t e = launch_shape(c, sh, n_iter);
   if (e != hipSuccess) return hip_fail(c, e, "FCA EM iteration");
   return post_check(c);
@@ -458,6 +492,7 @@ fca_status fca_set_params(fca_ctx* c, const float* v, const float* lam, const fc
     return fail(c, FCA_ERR_ARG, "misaligned pointer");
   const DevState& s = c->s;
   hipError_t e = hipSuccess;
+  ++c->version;
   if (v) e = fca::launch_pack_v(v, s.vs, c->F, c->N, c->J, s.Npad, c->stream);
   if (e == hipSuccess && lam && c->method == FCA_METHOD_AS)
     e = hipMemcpyAsync(s.lam, lam, sizeof(float) * c->F * c->J * c->I, hipMemcpyDeviceToDevice, c->stream);
@@ -525,6 +560,7 @@ void fca_destroy(fca_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   if (c->arena) (void)hipFree(c->arena);
+  if (c->tape) (void)hipFree(c->tape);
   delete c;
 }
 

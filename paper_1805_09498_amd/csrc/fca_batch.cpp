@@ -255,6 +255,7 @@ fca_status fca_batch_iterate(fca_batch* b, int n_iter) {
     fca_status st = tune(b);
     if (st != FCA_OK) return st;
   }
+  for (fca_ctx* c : b->ctx) ++c->version;
   hipError_t e;
   if (b->use_graph && b->stream != nullptr) {
     auto it = b->graphs.find(n_iter);

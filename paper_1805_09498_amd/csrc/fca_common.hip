@@ -32,6 +32,15 @@ __global__ void k_unpack_v(const float* __restrict__ vs, float* __restrict__ v, 
   for (int j = 0; j < J; ++j) v[((size_t)f * N + n) * J + j] = vs[((size_t)f * J + j) * Npad + n];
 }
 
+// xs [F][2I][Npad] -> x [F][N][I] (interleaved complex).
+__global__ void k_unpack_x(const float* __restrict__ xs, float2* __restrict__ x, int F, int N, int I, int Npad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)F * N) return;
+  const int f = (int)(t / N), n = (int)(t % N);
+  const float* src = xs + (size_t)f * 2 * I * Npad + n;
+  for (int i = 0; i < I; ++i) x[((size_t)f * N + n) * I + i] = make_float2(src[(size_t)i * Npad], src[(size_t)(I + i) * Npad]);
+}
+
 __global__ void k_check_finite(const float* __restrict__ a, long long n, int* flag) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -66,6 +75,10 @@ hipError_t launch_pack_v(const float* v, float* vs, int F, int N, int J, int Npa
 }
 hipError_t launch_unpack_v(const float* vs, float* v, int F, int N, int J, int Npad, hipStream_t st) {
   hipLaunchKernelGGL(k_unpack_v, dim3(blocks_for((long long)F * N, 256)), dim3(256), 0, st, vs, v, F, N, J, Npad);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_x(const float* xs, float2* x, int F, int N, int I, int Npad, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack_x, dim3(blocks_for((long long)F * N, 256)), dim3(256), 0, st, xs, x, F, N, I, Npad);
   return hipGetLastError();
 }
 hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream_t st) {

@@ -22,12 +22,32 @@ struct fca_ctx {
   int autotune;  // 1: time the candidate launch shapes once per (method, I, J, F, N)
   float* backup;  // state copy used while tuning: vs, lam, P (AS) or vs, R (EM)
   int last_waves, last_bpw;  // launch shape of the last iterate call (waves 0: streaming)
+  unsigned long long version;  // bumped by every call that changes the state
+  // Recording of the last fastfca_as_forward, for fastfca_as_backward.
+  void* tape;
+  size_t tape_bytes;
+  int tape_iters, tape_every;
+  int tape_waves, tape_bpw;           // launch shape of the recorded iterations
+  unsigned long long tape_version;    // version right after the recording
   std::string err;
 };
 
 namespace fca {
 // Save the iterated state of a context to its backup region, or restore it.
 hipError_t copy_state(fca_ctx* c, bool save);
+
+// Error setters of the context (the message is kept for fca_last_error).
+fca_status ctx_fail(fca_ctx* c, fca_status st, const std::string& msg);
+fca_status ctx_hip_fail(fca_ctx* c, hipError_t e, const char* where);
+
+// FastFCA-AS iterations of a context with its launch-shape choice (options,
+// tuner); the shape used is returned in *waves, *bpw (waves 0: streaming).
+fca_status as_iterate_chosen(fca_ctx* c, int n_iter, int* waves, int* bpw);
+// n_iter FastFCA-AS iterations of the state view s (the context's x and
+// scratch, any v / lambda / P) with a given launch shape.
+hipError_t as_iterate_view(fca_ctx* c, const DevState& s, int waves, int bpw, int n_iter);
+// After-launch checks of an iterate call (launch error, optional finiteness).
+fca_status post_iterate(fca_ctx* c);
 
 // The host-side argument checks of fca_init (no device access).
 fca_status validate_init(fca_method method, int F, int N, int I, int J, const void* x, const void* v0,

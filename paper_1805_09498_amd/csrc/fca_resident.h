@@ -48,8 +48,9 @@ __device__ __forceinline__ float sum_waves(const float* part, int stride, int k,
 
 // The body of one frequency-resident workgroup: bins f0 .. f0 + nb - 1 of the
 // problem s (nb in {1, 2}), n_iter hybrid iterations.
-template <int I, int J, int NPT>
-__device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int nb, int n_iter) {
+template <int I, int J, int NPT, bool kTrace = false>
+__device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int nb, int n_iter,
+                                                 const Trace& tr = Trace{}) {
   constexpr int VS = pad4(J * I);
   constexpr bool kOnePass = I * I * I <= 64;       // all I weighted sums in one sweep
   constexpr int VQ = kOnePass ? pad4(I * I * I) : pad4(I * I);
@@ -230,6 +231,15 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           Sr[a][b] = sum_waves(Qc, QSTRIDE, a * I + b, nw);
           Si[a][b] = (b > a) ? sum_waves(Qc, QSTRIDE, b * I + a, nw) : 0.f;
         }
+      if constexpr (kTrace) {
+        if (tb < I) {  // S_c packed: real parts on and above, imaginary parts below the diagonal
+          float* dst = tr.S + (size_t)it * tr.sstride + ((size_t)f * I + c) * I * I;
+#pragma unroll
+          for (int a = 0; a < I; ++a)
+#pragma unroll
+            for (int b = 0; b < I; ++b) dst[a * I + b] = (b >= a) ? Sr[a][b] : Si[b][a];
+        }
+      }
       const float fN = float(s.N);
       float ar[I], ai[I], pnr[I], pni[I];
 #pragma unroll
@@ -278,6 +288,21 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       }
     }
     __syncthreads();
+    if constexpr (kTrace) {  // the state after this iteration
+      const size_t off = (size_t)it * tr.stride;
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int n = tb + k * T;
+        if (n < s.N) {
+#pragma unroll
+          for (int j = 0; j < J; ++j) tr.v[off + ((size_t)f * J + j) * s.Npad + n] = v[k][j];
+        }
+      }
+      float2* Pit = reinterpret_cast<float2*>(reinterpret_cast<float*>(tr.P) + off);
+      for (int t = tb; t < I * I; t += T)
+        Pit[(size_t)f * I * I + t] = make_float2(sPr[bin][t / I][t % I], sPi[bin][t / I][t % I]);
+      for (int t = tb; t < J * I; t += T) tr.lam[off + (size_t)f * J * I + t] = sLam[bin][t];
+    }
   }
 
   // ---- write the state back ------------------------------------------------
@@ -300,6 +325,14 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_
   const int f0 = blockIdx.x * bpw;
   const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
   as_resident_body<I, J, NPT>(s, f0, nb, n_iter);
+}
+
+// The same as k_as_resident, recording the state after every iteration.
+template <int I, int J, int NPT>
+__global__ __launch_bounds__(kResMaxBlock) void k_as_resident_trace(DevState s, int n_iter, int bpw, Trace tr) {
+  const int f0 = blockIdx.x * bpw;
+  const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
+  as_resident_body<I, J, NPT, true>(s, f0, nb, n_iter, tr);
 }
 
 // Many problems of the same (I, J): workgroup g takes tile g = (problem,
@@ -489,6 +522,26 @@ hipError_t launch_as_iter_resident(const DevState& s, hipStream_t st, int n_iter
     hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, s, n_iter, bpw);
   else if (need <= 16 && mx >= 16)
     hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, s, n_iter, bpw);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int I, int J>
+hipError_t launch_as_iter_resident_trace(const DevState& s, hipStream_t st, int n_iter, int waves, int bpw,
+                                         const Trace& tr) {
+  const int T = (waves / bpw) * kWave;
+  const int need = (s.N + T - 1) / T;
+  constexpr int mx = res_max_npt<I, J>();
+  dim3 grid((s.F + bpw - 1) / bpw), block(waves * kWave);
+  if (need <= 4)
+    hipLaunchKernelGGL((k_as_resident_trace<I, J, 4>), grid, block, 0, st, s, n_iter, bpw, tr);
+  else if (need <= 8 && mx >= 8)
+    hipLaunchKernelGGL((k_as_resident_trace<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, s, n_iter, bpw, tr);
+  else if (need <= 12 && mx >= 12)
+    hipLaunchKernelGGL((k_as_resident_trace<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, s, n_iter, bpw, tr);
+  else if (need <= 16 && mx >= 16)
+    hipLaunchKernelGGL((k_as_resident_trace<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, s, n_iter, bpw, tr);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -42,6 +42,39 @@ struct DevState {
   int* flag;      // [1]
 };
 
+// Arguments of the adjoint kernels: the state before (t) and after (n) one
+// iteration, the adjoints of the state after it (in) and of the state before
+// it (out), and the mixture's adjoint xb [F][2I][Npad] (accumulated).
+struct AdjIter {
+  const float* S_t;   // eq. 23 sums of the iteration ([F][I][I*I] packed), or NULL: recomputed
+  const float* v_t;
+  const float* lam_t;
+  const float2* P_t;
+  const float* v_n;
+  const float* lam_n;
+  const float* vb_in;
+  const float* lb_in;
+  const float2* Pb_in;
+  float* vb_out;
+  float* lb_out;
+  float2* Pb_out;
+  float* xb;
+};
+
+// Where a recording run of the frequency-resident FastFCA-AS kernel writes
+// the state after each of its iterations: iteration it writes v, lambda and P
+// at offset it * stride (floats) from v / lam / P (the layouts of DevState),
+// and the eq. 23 sums S_c (packed Hermitian, [F][I][I*I]) at it * sstride
+// from S.
+struct Trace {
+  float* v;
+  float* lam;
+  float2* P;
+  float* S;
+  long long stride;
+  long long sstride;
+};
+
 // Host launchers of one (I, J) instantiation.
 struct KernelSet {
   hipError_t (*as_iter_stream)(const DevState&, hipStream_t);
@@ -58,12 +91,17 @@ struct KernelSet {
   hipError_t (*em_wiener)(const DevState&, hipStream_t, float2* out);
   hipError_t (*em_from_as)(const DevState&, hipStream_t);
   hipError_t (*em_rinv)(const DevState&, hipStream_t);
+  hipError_t (*as_iter_resident_trace)(const DevState&, hipStream_t, int n_iter, int waves, int bpw,
+                                       const Trace&);
+  hipError_t (*adj_iter)(const DevState&, const AdjIter&, hipStream_t);
+  hipError_t (*adj_wiener)(const DevState&, const float2* gout, const AdjIter&, hipStream_t);
 };
 
 // Non-templated kernels' launchers (fca_common.hip).
 hipError_t launch_pack_x(const float2* x, float* xs, int F, int N, int I, int Npad, hipStream_t st);
 hipError_t launch_pack_v(const float* v, float* vs, int F, int N, int J, int Npad, hipStream_t st);
 hipError_t launch_unpack_v(const float* vs, float* v, int F, int N, int J, int Npad, hipStream_t st);
+hipError_t launch_unpack_x(const float* xs, float2* x, int F, int N, int I, int Npad, hipStream_t st);
 hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream_t st);
 hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st);
 

@@ -5,7 +5,9 @@ The functions carry the names of the C ABI (include/fastfca.h):
 ``fca_init``, ``fastfca_as_iterate``, ``fca_em_iterate``,
 ``fca_wiener_separate``, ``fca_loglik``, ``fca_get_params``,
 ``fca_set_params``, ``fca_set_option``, ``fca_get_option``, ``fca_last_error``,
-``fca_destroy``.
+``fca_destroy``, the batch calls ``fca_batch_*`` and the derivative calls
+``fastfca_as_forward`` / ``fastfca_as_backward`` (``autograd.py`` wraps them
+in a ``torch.autograd.Function``).
 Arrays are torch tensors on the GPU in the ABI layouts (complex64 /
 float32, C-contiguous); PyTorch provides the device memory and the stream.
 
@@ -35,7 +37,8 @@ EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_sepa
             "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
             "fca_get_option", "fca_last_error", "fca_destroy",
             "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
-            "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy")
+            "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
+            "fastfca_as_forward", "fastfca_as_backward")
 
 
 def _load():
@@ -81,6 +84,10 @@ def _load():
     lib.fca_batch_last_error.restype = c
     lib.fca_batch_destroy.argtypes = [vp]
     lib.fca_batch_destroy.restype = None
+    lib.fastfca_as_forward.argtypes = [vp, i, i, vp]
+    lib.fastfca_as_forward.restype = i
+    lib.fastfca_as_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.fastfca_as_backward.restype = i
     return lib
 
 
@@ -218,6 +225,35 @@ def fca_get_option(ctx, key):
     out = ctypes.c_longlong()
     _check(lib.fca_get_option(ctx.handle, key.encode(), ctypes.byref(out)), ctx)
     return out.value
+
+
+def fastfca_as_forward(ctx, n_iter, ckpt_every=5, out=None):
+    """n_iter recorded iterations, then the Wiener filter; returns (or fills)
+    out [J][F][N][I] complex64."""
+    if out is None:
+        with torch.cuda.stream(ctx.stream):
+            out = torch.empty((ctx.J, ctx.F, ctx.N, ctx.I), dtype=torch.complex64, device="cuda")
+    p = _ptr(out, torch.complex64, (ctx.J, ctx.F, ctx.N, ctx.I), "out")
+    _check(lib.fastfca_as_forward(ctx.handle, int(n_iter), int(ckpt_every), p), ctx)
+    return out
+
+
+def fastfca_as_backward(ctx, grad_out, need=(True, True, True, True)):
+    """Derivatives of the last fastfca_as_forward for dL/d(out) = grad_out:
+    returns (dx [F][N][I], dv0 [F][N][J], dlam0 [F][J][I], dP0 [F][I][I]),
+    None where need is False."""
+    F, N, I, J = ctx.F, ctx.N, ctx.I, ctx.J
+    g = _ptr(grad_out, torch.complex64, (J, F, N, I), "grad_out")
+    shapes = (((F, N, I), torch.complex64), ((F, N, J), torch.float32), ((F, J, I), torch.float32),
+              ((F, I, I), torch.complex64))
+    outs = []
+    with torch.cuda.stream(ctx.stream):
+        for want, (shp, dt) in zip(need, shapes):
+            outs.append(torch.empty(shp, dtype=dt, device="cuda") if want else None)
+    ptrs = [None if o is None else ctypes.c_void_p(o.data_ptr()) for o in outs]
+    _check(lib.fastfca_as_backward(ctx.handle, g, *ptrs), ctx)
+    ctx._keep_grad = grad_out   # referenced until the stream has consumed it
+    return tuple(outs)
 
 
 def fca_destroy(ctx):

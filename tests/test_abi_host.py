@@ -47,7 +47,8 @@ def test_header_declares_the_expected_calls():
         "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
         "fca_get_option", "fca_last_error", "fca_destroy",
         "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
-        "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy"])
+        "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
+        "fastfca_as_forward", "fastfca_as_backward"])
 
 
 def test_every_declared_function_is_exported(lib):
@@ -109,10 +110,19 @@ def test_batch_init_rejects_bad_arguments(lib):
     assert b"mixture 1" in lib.fca_batch_last_error(None)
 
 
+def test_null_context_derivative_calls(lib):
+    vp = ctypes.c_void_p
+    lib.fastfca_as_forward.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.fastfca_as_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    assert lib.fastfca_as_forward(None, 3, 1, None) == -1
+    assert lib.fastfca_as_backward(None, FAKE, None, None, None, None) == -1
+
+
 def test_binding_has_no_fallback():
     """The Python binding loads the HIP library or fails: there is no CPU
     path and no import of the oracle."""
-    src = open(os.path.join(ROOT, "paper_1805_09498_amd", "fastfca.py")).read()
-    assert "oracle" not in src and "numpy" not in src
+    for name in ("fastfca.py", "autograd.py"):
+        src = open(os.path.join(ROOT, "paper_1805_09498_amd", name)).read()
+        assert "oracle" not in src and "numpy" not in src, name
     import paper_1805_09498_amd.fastfca as ff
     assert ff.lib._name == ff.LIB_PATH
