@@ -8,7 +8,8 @@ helper or constant with the HIP library under ``paper_1805_09498_amd/``.
 Every routine is a plain, slow, complex128/float64 transcription of what the
 paper defines, vectorised over frequency bins and frames with numpy; the
 module ``unrolled`` restates the same steps with plain torch CPU operations so
-that torch's autograd gives reference derivatives of the unrolled method.
+that torch's autograd gives reference derivatives of the unrolled method, and
+``stft`` holds the STFT analysis / overlap-add synthesis of the experiments.
 Array layouts (the same as the C ABI of the library so that tests can feed
 both the same arrays):
 

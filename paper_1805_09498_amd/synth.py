@@ -167,3 +167,23 @@ def make_batch(n_mix=64, F=513, seed=4000, n_range=(200, 2000), i_choices=(2, 3,
         N = int(rng.integers(n_range[0], n_range[1] + 1))
         out.append(make_problem(I, J, F, N, seed=seed * 1000 + k, spatial="ula", psd="gamma"))
     return out
+
+
+def make_waveforms(I, J, L, seed, rir_len=256, fs=16000):
+    """Multichannel mixture waveforms: J sources (white noise under a slow
+    random envelope, a stand-in for speech), each filtered by I random room
+    responses (exponentially decaying noise, rir_len taps, a direct path at
+    tap 0) and summed.  Returns (mix [I][L], images [J][I][L]) in float64."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    t = np.arange(L) / fs
+    images = np.zeros((J, I, L))
+    for j in range(J):
+        env = np.zeros(L)
+        for k in range(4):                        # a few slow modulations per source
+            env += rng.uniform(0.2, 1.0) * (1 + np.sin(2 * np.pi * rng.uniform(0.5, 4.0) * t + rng.uniform(0, 2 * np.pi)))
+        src = rng.standard_normal(L) * env
+        for i in range(I):
+            h = rng.standard_normal(rir_len) * np.exp(-np.arange(rir_len) / (rir_len / 6.0))
+            h[0] = 1.0
+            images[j, i] = np.convolve(src, h)[:L]
+    return images.sum(axis=0), images

@@ -65,3 +65,11 @@ def test_uneven_batch_ranges():
     for p in mixes:
         F, N, I, J = p.shape
         assert I in (2, 3, 4, 6) and 2 <= J <= I + 1 and 200 <= N <= 2000 and F == 9
+
+
+def test_waveform_mixture_is_the_sum_of_images_and_seeded():
+    mix, images = synth.make_waveforms(3, 2, 4000, seed=5, rir_len=64)
+    assert mix.shape == (3, 4000) and images.shape == (2, 3, 4000)
+    np.testing.assert_allclose(mix, images.sum(axis=0), rtol=0, atol=1e-12)
+    mix2, _ = synth.make_waveforms(3, 2, 4000, seed=5, rir_len=64)
+    np.testing.assert_array_equal(mix, mix2)
