@@ -236,6 +236,35 @@ fca_status fastfca_as_forward(fca_ctx *ctx, int n_iter, int ckpt_every, fca_c64 
 fca_status fastfca_as_backward(fca_ctx *ctx, const fca_c64 *grad_out, fca_c64 *grad_x, float *grad_v0,
                                float *grad_lam0, fca_c64 *grad_P0);
 
+/* ------------------------------------------------------------------------
+ * STFT front and back end (the analysis and synthesis settings of the
+ * paper's experiments, Table 1: 16 kHz, frame 1024, shift 512, square root
+ * of a Hann window for both), so that multichannel waveforms go in and
+ * separated waveforms come out.  frame: a power of two in 16..4096; hop:
+ * divides frame, at most frame / 2.  Frame n covers samples
+ * n hop - (frame - hop) .. n hop - (frame - hop) + frame - 1 (zero outside
+ * the signal), so every sample lies in frame / hop frames; the window is
+ * w[t] = sin(pi t / frame); bins f = 0 .. frame / 2.  Errors: FCA_ERR_ARG
+ * (message in fca_last_error(NULL)), FCA_ERR_HIP.
+ * ------------------------------------------------------------------------ */
+
+/* Spectrum shape of an L-sample signal: *F = frame / 2 + 1,
+ * *N = floor((L - 1 + frame - hop) / hop) + 1.  Host only. */
+fca_status fca_stft_shape(int L, int frame, int hop, int *F, int *N);
+
+/* Analysis of C channels: wav [C][L] float (device) -> X [F][N][C] complex
+ * (device; the mixture layout of fca_init).  Asynchronous. */
+fca_status fca_stft(const float *wav, int C, int L, int frame, int hop, fca_c64 *X, void *hip_stream);
+
+/* Synthesis of J signals of C channels each: S [J][F][N][C] complex (device;
+ * the layout of fca_wiener_separate) -> wav [J][C][L] float (device), the
+ * inverse of fca_stft (overlap-add of windowed inverse transforms, scaled by
+ * 2 hop / frame; only the real parts of bins 0 and frame / 2 are used).  N
+ * must be the frame count of an L-sample signal.  Allocates J*C*N*frame
+ * floats of stream-ordered scratch for the call.  Asynchronous. */
+fca_status fca_istft(const fca_c64 *S, int J, int C, int N, int frame, int hop, int L, float *wav,
+                     void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

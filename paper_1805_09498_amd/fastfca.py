@@ -7,7 +7,8 @@ The functions carry the names of the C ABI (include/fastfca.h):
 ``fca_set_params``, ``fca_set_option``, ``fca_get_option``, ``fca_last_error``,
 ``fca_destroy``, the batch calls ``fca_batch_*`` and the derivative calls
 ``fastfca_as_forward`` / ``fastfca_as_backward`` (``autograd.py`` wraps them
-in a ``torch.autograd.Function``).
+in a ``torch.autograd.Function``) and the STFT calls ``fca_stft_shape``,
+``fca_stft``, ``fca_istft``.
 Arrays are torch tensors on the GPU in the ABI layouts (complex64 /
 float32, C-contiguous); PyTorch provides the device memory and the stream.
 
@@ -38,7 +39,7 @@ EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_sepa
             "fca_get_option", "fca_last_error", "fca_destroy",
             "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
             "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
-            "fastfca_as_forward", "fastfca_as_backward")
+            "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft")
 
 
 def _load():
@@ -88,6 +89,12 @@ def _load():
     lib.fastfca_as_forward.restype = i
     lib.fastfca_as_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.fastfca_as_backward.restype = i
+    lib.fca_stft_shape.argtypes = [i, i, i, ip, ip]
+    lib.fca_stft_shape.restype = i
+    lib.fca_stft.argtypes = [vp, i, i, i, i, vp, vp]
+    lib.fca_stft.restype = i
+    lib.fca_istft.argtypes = [vp, i, i, i, i, i, i, vp, vp]
+    lib.fca_istft.restype = i
     return lib
 
 
@@ -337,3 +344,36 @@ def fca_batch_destroy(batch):
     if batch.handle is not None and batch.handle.value:
         lib.fca_batch_destroy(batch.handle)
     batch.handle = ctypes.c_void_p()
+
+
+def fca_stft_shape(L, frame=1024, hop=512):
+    F, N = ctypes.c_int(), ctypes.c_int()
+    _check(lib.fca_stft_shape(int(L), int(frame), int(hop), ctypes.byref(F), ctypes.byref(N)))
+    return F.value, N.value
+
+
+def fca_stft(wav, frame=1024, hop=512, stream=None):
+    """wav [C][L] float32 (GPU) -> X [F][N][C] complex64, the mixture layout."""
+    if wav.dim() != 2:
+        raise ValueError("wav must be [C][L]")
+    C, L = wav.shape
+    F, N = fca_stft_shape(L, frame, hop)
+    sh, s = _stream_handle(stream)
+    with torch.cuda.stream(s):
+        X = torch.empty((F, N, C), dtype=torch.complex64, device="cuda")
+    _check(lib.fca_stft(_ptr(wav, torch.float32, (C, L), "wav"), C, L, int(frame), int(hop),
+                        ctypes.c_void_p(X.data_ptr()), sh))
+    return X
+
+
+def fca_istft(S, L, frame=1024, hop=512, stream=None):
+    """S [J][F][N][C] complex64 (GPU) -> waveforms [J][C][L] float32."""
+    if S.dim() != 4:
+        raise ValueError("S must be [J][F][N][C]")
+    J, F, N, C = S.shape
+    sh, s = _stream_handle(stream)
+    with torch.cuda.stream(s):
+        wav = torch.empty((J, C, int(L)), dtype=torch.float32, device="cuda")
+    _check(lib.fca_istft(_ptr(S, torch.complex64, (J, F, N, C), "S"), J, C, N, int(frame), int(hop), int(L),
+                         ctypes.c_void_p(wav.data_ptr()), sh))
+    return wav

@@ -120,13 +120,23 @@ def make_problem(I, J, F, N, seed, spatial="rank1", psd="gamma",
         x[f0:f1] = sj.sum(axis=2)
         if with_sources:
             s[:, f0:f1] = np.moveaxis(sj, 2, 0)
-    P0 = np.eye(I) + 0.1 * _cn(rng_init, (F, I, I))
-    lam0 = rng_init.uniform(0.5, 1.5, size=(F, J, I))
+    v0, lam0, P0 = init_params(x, J, rng_init)
+    return Problem(x=x, v0=v0, lam0=lam0, P0=P0, s=s, v_true=v, R_true=R)
+
+
+def init_params(x, J, rng_or_seed):
+    """Seeded initial parameters for a mixture x [F][N][I] (no estimation):
+    P = 1 + 0.1 G with G complex normal, lambda ~ U[0.5, 1.5], and
+    v = (|x|^2 / I + 1e-3 mean_n |x|^2 / I) U[0.5, 1.5].  Returns (v0, lam0, P0)."""
+    rng = np.random.default_rng(rng_or_seed)
+    F, N, I = x.shape
+    P0 = np.eye(I) + 0.1 * _cn(rng, (F, I, I))
+    lam0 = rng.uniform(0.5, 1.5, size=(F, J, I))
     pw = (np.abs(x) ** 2).sum(axis=2) / I                      # [F][N]
     base = pw + 1e-3 * pw.mean(axis=1, keepdims=True)
     base = np.where(base > 0, base, 1e-6)
-    v0 = base[:, :, None] * rng_init.uniform(0.5, 1.5, size=(F, N, J))
-    return Problem(x=x, v0=v0, lam0=lam0, P0=P0, s=s, v_true=v, R_true=R)
+    v0 = base[:, :, None] * rng.uniform(0.5, 1.5, size=(F, N, J))
+    return v0, lam0, P0
 
 
 def random_hpd(rng_or_seed, F, J, I, ridge=0.1):

@@ -48,7 +48,7 @@ def test_header_declares_the_expected_calls():
         "fca_get_option", "fca_last_error", "fca_destroy",
         "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
         "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
-        "fastfca_as_forward", "fastfca_as_backward"])
+        "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft"])
 
 
 def test_every_declared_function_is_exported(lib):
@@ -126,3 +126,25 @@ def test_binding_has_no_fallback():
         assert "oracle" not in src and "numpy" not in src, name
     import paper_1805_09498_amd.fastfca as ff
     assert ff.lib._name == ff.LIB_PATH
+
+
+@pytest.mark.parametrize("L,W,H", [(160000, 1024, 512), (1, 16, 8), (16001, 2048, 256), (5000, 64, 16)])
+def test_stft_shape_matches_the_framing_rule(lib, L, W, H):
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.fca_stft_shape.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip]
+    F, N = ctypes.c_int(), ctypes.c_int()
+    assert lib.fca_stft_shape(L, W, H, ctypes.byref(F), ctypes.byref(N)) == 0
+    assert (F.value, N.value) == (W // 2 + 1, (L - 1 + W - H) // H + 1)
+
+
+@pytest.mark.parametrize("W,H", [(1000, 500), (8, 4), (8192, 4096), (1024, 1024), (1024, 300), (1024, 0)])
+def test_stft_rejects_bad_frames_on_the_host(lib, W, H):
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.fca_stft_shape.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip]
+    F, N = ctypes.c_int(), ctypes.c_int()
+    assert lib.fca_stft_shape(1000, W, H, ctypes.byref(F), ctypes.byref(N)) == -1
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    lib.fca_stft.argtypes = [vp, i, i, i, i, vp, vp]
+    assert lib.fca_stft(FAKE, 2, 1000, W, H, FAKE, None) == -1
+    lib.fca_istft.argtypes = [vp, i, i, i, i, i, i, vp, vp]
+    assert lib.fca_istft(FAKE, 2, 2, 3, W, H, 1000, FAKE, None) == -1
