@@ -3,7 +3,7 @@
 A step is one whole separation job on the 10 s speech-scale workload
 (I = J = 3 microphones/sources, F = 513 bins, N = 626 frames, 100 hybrid
 iterations, complex64 data with FP32 arithmetic): reset the parameters to the
-seeded initial point, run the 100 iterations (Section 4.4 of the paper),
+seeded initial point, run the 100 iterations (Section 4.3 of the paper),
 evaluate the log-likelihood (eq. 14) and apply the multichannel Wiener filter
 (eq. 3).  Inputs are resident in device memory before timing starts.
 

@@ -88,7 +88,7 @@ fca_status fca_init(fca_ctx **out, fca_method method, int F, int N, int I, int J
                     const fca_c64 *x, const float *v0, const float *lam0,
                     const fca_c64 *P0, const fca_c64 *R0, void *hip_stream);
 
-/* Run n_iter hybrid iterations of FastFCA-AS (Section 4.4): the EM update of
+/* Run n_iter hybrid iterations of FastFCA-AS (Section 4.3): the EM update of
  * v and lambda (eq. 15-20), then K fixed-point updates of every P(f) (eq. 23,
  * K from the "K" option, default 1) with the new v and lambda.
  * n_iter >= 0.  FCA_ERR_STATE on an EM context.  Asynchronous. */
@@ -176,7 +176,7 @@ fca_status fca_batch_init(fca_batch **out, int n_mix, const int *F, const int *N
                           const int *J, const fca_c64 *const *x, const float *const *v0,
                           const float *const *lam0, const fca_c64 *const *P0, void *hip_stream);
 
-/* n_iter hybrid iterations of every mixture (Section 4.4).  The first call
+/* n_iter hybrid iterations of every mixture (Section 4.3).  The first call
  * times the candidate launch shapes per (I, J) group (synchronising the
  * stream; the state is restored; FASTFCA_TUNE_CACHE as for fca_set_option's
  * "autotune").  Asynchronous otherwise. */
@@ -206,7 +206,7 @@ void fca_batch_destroy(fca_batch *b);
 
 /* ------------------------------------------------------------------------
  * Derivatives of the unrolled method (reverse mode): a recorded run of
- * hybrid iterations (Section 4.4) followed by the Wiener filter (eq. 3 with
+ * hybrid iterations (Section 4.3) followed by the Wiener filter (eq. 3 with
  * eq. 15), and the derivative of a real loss on its output with respect to
  * the mixture and the starting parameters.
  * ------------------------------------------------------------------------ */

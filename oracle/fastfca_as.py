@@ -1,9 +1,9 @@
 """FastFCA-AS (Section 4 of the paper), FP64 oracle.
 
 Test infrastructure only (see the package docstring).  One hybrid iteration
-is the two steps of Section 4.4: an EM update of (Lambda_j, v_j) with P(f)
-held fixed (Section 4.4.1, eq. 15-20), then the fixed-point update of P(f)
-(Section 4.4.2, eq. 21-23).
+is the two steps of Section 4.3: an EM update of (Lambda_j, v_j) with P(f)
+held fixed (Section 4.3.1, eq. 15-20), then the fixed-point update of P(f)
+(Section 4.3.2, eq. 21-23).
 
 Readings of the paper used here:
   * v_j is updated first with the current Lambda_j (eq. 19) and Lambda_j then
@@ -106,7 +106,7 @@ def as_fpi_step(x, v, lam, P, K=1):
 
 
 def fastfca_as_step(x, v, lam, P, K=1):
-    """One hybrid iteration of FastFCA-AS (Section 4.4): EM on (Lambda, v),
+    """One hybrid iteration of FastFCA-AS (Section 4.3): EM on (Lambda, v),
     then the fixed-point update of P with the new (Lambda, v).
 
     Returns (v_new, lam_new, P_new).

@@ -2,7 +2,7 @@
 reference for reverse-mode derivatives.
 
 Test infrastructure only (see the package docstring).  The same steps as
-``fastfca_as.py`` (Section 4.4: the EM update of eq. 15-20, then the
+``fastfca_as.py`` (Section 4.3: the EM update of eq. 15-20, then the
 fixed-point update of eq. 23) and the multichannel Wiener filter (eq. 3 with
 the covariances of eq. 12 and eq. 15), written with torch operations so that
 torch's autograd gives the derivative of a loss on the separated images
@@ -23,7 +23,7 @@ def _h(a):
 
 
 def as_step(x, v, lam, P):
-    """One hybrid iteration (Section 4.4), K = 1.
+    """One hybrid iteration (Section 4.3), K = 1.
 
     E-step in the basis y~ = P^H y (eq. 16-17, diagonal), v update (eq. 19)
     with the current Lambda, Lambda update (eq. 20) with the new v, then every

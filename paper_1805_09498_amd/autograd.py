@@ -1,7 +1,7 @@
 """Differentiable unrolled FastFCA-AS for PyTorch.
 
 ``unrolled_separate(x, v0, lam0, P0, n_iter, ckpt_every)`` runs n_iter hybrid
-iterations (Section 4.4 of the paper) from (v0, lam0, P0) and returns the
+iterations (Section 4.3 of the paper) from (v0, lam0, P0) and returns the
 Wiener estimates of the sources (eq. 3 with eq. 15), [J][F][N][I] complex64.
 Its backward pass is the library's hand-written adjoint
 (``fastfca_as_backward``): gradients reach x, v0, lam0 and P0, and the

@@ -1,5 +1,5 @@
 // Reverse-mode derivatives (adjoints) of FastFCA-AS: one hybrid iteration
-// (Section 4.4: eq. 15-20, then eq. 23) and the multichannel Wiener filter
+// (Section 4.3: eq. 15-20, then eq. 23) and the multichannel Wiener filter
 // (eq. 3 with eq. 15).  Given dL/d(outputs) they produce dL/d(inputs) for a
 // real loss L; a complex quantity z carries dL/dRe z + i dL/dIm z.
 //

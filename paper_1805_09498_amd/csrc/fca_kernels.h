@@ -1,6 +1,6 @@
 // Templated kernels of libfastfca, instantiated per (I, J) by fca_inst_I*.hip.
 //
-// FastFCA-AS iteration (Section 4.4 of the paper), streaming form, three
+// FastFCA-AS iteration (Section 4.3 of the paper), streaming form, three
 // launches per hybrid iteration:
 //   as_pass_a  per point: y = P^H x, d_i = sum_j v_j lambda_ji, diagonal
 //              posterior statistics (eq. 16-17), v update (eq. 19); per tile

@@ -1,4 +1,4 @@
-"""Pins of the oracle's fixed-point update of P(f) (Section 4.4.2, eq. 21-23).
+"""Pins of the oracle's fixed-point update of P(f) (Section 4.3.2, eq. 21-23).
 
 * eq. 21 equals a central finite-difference Wirtinger derivative of L2.
 * The column-wise update (eq. 23) equals the dense vectorised solve (eq. 22).
@@ -92,7 +92,7 @@ def test_inner_iterations_reuse_weighted_covariances():
 
 
 def test_operation_counts_quoted_in_the_paper():
-    """Section 3.4 and 4.5: (J+N)F inversions and 2JNF multiplications per FCA
+    """Sections 3.4 and 4.4: (J+N)F inversions and 2JNF multiplications per FCA
     iteration, (I+1)FK inversions per FastFCA-AS iteration."""
     I = J = 3; N = 249; F = 512; K = 1
     assert (J + N) * F == 129024

@@ -1,4 +1,4 @@
-"""GPU parity of FastFCA-AS (Section 4.4) against the FP64 oracle, through
+"""GPU parity of FastFCA-AS (Section 4.3) against the FP64 oracle, through
 the C ABI, on both execution paths (frequency-resident and streaming)."""
 
 import numpy as np
