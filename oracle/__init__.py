@@ -42,11 +42,13 @@ from .fastfca_as import (
     wiener_as,
     as_wirtinger_grad,
     as_fpi_dense_vec,
+    as_gradient_p_step,
+    fastfca_as_step_grad,
 )
 
 __all__ = [
     "fca_model_cov", "fca_estep", "fca_mstep", "fca_em_step", "loglik_fca",
     "wiener_fca", "as_spatial_cov", "as_estep", "as_em_half_step",
     "as_fpi_step", "fastfca_as_step", "loglik_as", "wiener_as",
-    "as_wirtinger_grad", "as_fpi_dense_vec",
+    "as_wirtinger_grad", "as_fpi_dense_vec", "as_gradient_p_step", "fastfca_as_step_grad",
 ]

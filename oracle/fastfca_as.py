@@ -105,6 +105,32 @@ def as_fpi_step(x, v, lam, P, K=1):
     return P
 
 
+def as_gradient_p_step(x, v, lam, P, mu, natural=False):
+    """A gradient-type update of P(f) in place of the fixed-point step (the
+    alternatives Section 4.5 names).  With g = (1/N) dL2/dP* (eq. 21) at the
+    given v, Lambda:
+
+      gradient ascent:               P <- P + mu g
+      natural (relative) gradient:   P <- P + mu P P^H g
+
+    The second is the steepest-ascent direction under the metric that makes
+    the step equivariant to x -> A x, P -> A^-H P.
+    """
+    P = np.asarray(P, dtype=np.complex128)
+    N = np.asarray(x).shape[1]
+    g = as_wirtinger_grad(x, v, lam, P) / N
+    if natural:
+        return P + mu * np.einsum("fab,fcb,fcd->fad", P, np.conj(P), g)
+    return P + mu * g
+
+
+def fastfca_as_step_grad(x, v, lam, P, mu, natural=False):
+    """A hybrid iteration with the gradient-type P update: the EM step on
+    (Lambda, v), then as_gradient_p_step with the new (v, Lambda)."""
+    v_new, lam_new = as_em_half_step(x, v, lam, P)
+    return v_new, lam_new, as_gradient_p_step(x, v_new, lam_new, P, mu, natural)
+
+
 def fastfca_as_step(x, v, lam, P, K=1):
     """One hybrid iteration of FastFCA-AS (Section 4.3): EM on (Lambda, v),
     then the fixed-point update of P with the new (Lambda, v).
