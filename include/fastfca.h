@@ -122,10 +122,17 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
                           const fca_c64 *P_or_R);
 
 /* Options: "K" (fixed-point steps per hybrid iteration, 1..64, default 1),
+ * "p_update" (FastFCA-AS only; how step 2 of a hybrid iteration updates P:
+ * 0 = the fixed-point update of eq. 23 (default), 1 = gradient ascent
+ * P + mu g, 2 = natural (relative) gradient P + mu P P^H g, with
+ * g = (1/N) dL2/dP* of eq. 21 at the new v, lambda and mu the real option
+ * "p_step" (default 0.1) -- the alternatives named in Section 4.5; K applies
+ * to the fixed-point update only),
  * "check_finite" (0/1: after each iterate call, synchronise and return
  * FCA_ERR_NONFINITE if a parameter is NaN/Inf), "path" (0 = automatic,
  * 1 = force the frequency-resident kernels, 2 = force the streaming
- * kernels; K > 1 at I > 4 always uses the streaming kernels), "waves"
+ * kernels; K > 1 or the gradient P step at I > 4 always use the streaming
+ * kernels), "waves"
  * (64-lane waves per workgroup of the frequency-resident
  * kernels: 0 = automatic, 1, 2 or 4), "bins_per_wg" (frequency bins per
  * workgroup of the frequency-resident FastFCA-AS kernel: 0 = automatic, 1 or
@@ -143,7 +150,13 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * bitwise reproducible for a given launch shape. */
 fca_status fca_set_option(fca_ctx *ctx, const char *key, long long value);
 
-/* Read an option ("K", "check_finite", "path", "waves", "bins_per_wg",
+/* Real-valued options: "p_step" (step size mu of the gradient-type P
+ * updates, in (0, 1000], default 0.1).  FCA_ERR_ARG for unknown keys or
+ * values out of range. */
+fca_status fca_set_option_f64(fca_ctx *ctx, const char *key, double value);
+fca_status fca_get_option_f64(fca_ctx *ctx, const char *key, double *value);
+
+/* Read an option ("K", "p_update", "check_finite", "path", "waves", "bins_per_wg",
  * "autotune": the configured values) or the launch shape the last iterate
  * call used ("last_waves": waves per workgroup, 0 = streaming kernels, -1 =
  * no call yet; "last_bins_per_wg").  value is a host pointer.  Unknown keys
@@ -217,8 +230,8 @@ void fca_batch_destroy(fca_batch *b);
  * (device, may be NULL).  The recording lives in library-owned device memory
  * (ceil(n_iter / ckpt_every) + ckpt_every + 1 copies of (v, lambda, P), plus
  * the adjoint buffers) until the next call of this function or
- * fca_destroy.  n_iter >= 0, ckpt_every >= 1.  FCA_ERR_UNSUPPORTED when the
- * "K" option is not 1.  Asynchronous (a context's first iterations may run
+ * fca_destroy.  n_iter >= 0, ckpt_every >= 1.  FCA_ERR_UNSUPPORTED unless the
+ * "K" option is 1 and "p_update" is 0.  Asynchronous (a context's first iterations may run
  * the launch-shape tuner, see "autotune"). */
 fca_status fastfca_as_forward(fca_ctx *ctx, int n_iter, int ckpt_every, fca_c64 *out);
 

@@ -103,7 +103,8 @@ fca_status fastfca_as_forward(fca_ctx* c, int n_iter, int ckpt_every, fca_c64* o
   if (c->method != FCA_METHOD_AS) return fca::ctx_fail(c, FCA_ERR_STATE, "fastfca_as_forward on an FCA EM context");
   if (n_iter < 0 || ckpt_every < 1) return fca::ctx_fail(c, FCA_ERR_ARG, "n_iter must be >= 0 and ckpt_every >= 1");
   if (out && !aligned(out, 8)) return fca::ctx_fail(c, FCA_ERR_ARG, "out must be an 8-byte aligned device pointer");
-  if (c->s.K != 1) return fca::ctx_fail(c, FCA_ERR_UNSUPPORTED, "the recorded forward supports K = 1 only");
+  if (c->s.K != 1 || c->s.p_update != 0)
+    return fca::ctx_fail(c, FCA_ERR_UNSUPPORTED, "the recorded forward supports the fixed-point step with K = 1 only");
   const int every = ckpt_every < n_iter ? ckpt_every : (n_iter > 0 ? n_iter : 1);
   const TapeLayout t = layout(c, n_iter, every);
   const size_t bytes = sizeof(float) * t.total_floats;

@@ -83,11 +83,11 @@ struct Shape {
 };
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int>, Shape> g_tuned;  // (method, I, J, F, N, K)
+std::map<std::tuple<int, int, int, int, int, int, int>, Shape> g_tuned;  // (method, I, J, F, N, K, P step)
 
 bool shape_fits(const fca_ctx* c, Shape sh) {
   if (sh.waves == 0) return true;
-  if (c->method == FCA_METHOD_AS && c->s.K > 1 && c->I > fca::kResMaxIK) return false;
+  if (c->method == FCA_METHOD_AS && (c->s.K > 1 || c->s.p_update == 1) && c->I > fca::kResMaxIK) return false;
   return c->method == FCA_METHOD_AS ? c->ks->as_resident_fits(c->N, sh.waves, sh.bpw) != 0
                                     : (sh.bpw == 1 && c->ks->em_resident_fits(c->N, sh.waves) != 0);
 }
@@ -152,7 +152,7 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
   if (c->path == 1) {
     bool any = false;
     for (int k = 0; k < ncand; ++k) any = any || (cands[k].waves > 0 && shape_fits(c, cands[k]));
-    if (!any) return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this problem (N, or K > 1 at I > 4)");
+    if (!any) return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this problem (N, or K > 1 / gradient P step at I > 4)");
   }
   const bool forced = c->waves > 0 || c->bpw > 0;
   if (forced || !c->autotune) {
@@ -164,11 +164,11 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
       if (shape_fits(c, sh)) { *out = sh; return FCA_OK; }
     }
     if (c->path == 1)
-      return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this N with this launch shape");
+      return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this problem with this launch shape");
     *out = Shape{0, 0};
     return FCA_OK;
   }
-  const auto key = std::make_tuple((int)c->method, c->I, c->J, c->F, c->N, c->s.K);
+  const auto key = std::make_tuple((int)c->method, c->I, c->J, c->F, c->N, c->s.K, c->s.p_update);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
@@ -180,7 +180,7 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
   const std::string disk_key = fca::tune_key_prefix() + (c->method == FCA_METHOD_AS ? " as" : " em") +
                                " I=" + std::to_string(c->I) + " J=" + std::to_string(c->J) +
                                " F=" + std::to_string(c->F) + " N=" + std::to_string(c->N) +
-                               " K=" + std::to_string(c->s.K);
+                               " K=" + std::to_string(c->s.K) + " pstep=" + std::to_string(c->s.p_update);
   {
     Shape sh{0, 0};
     if (c->path == 0 && fca::tune_cache_get(disk_key, &sh.waves, &sh.bpw) && shape_fits(c, sh)) {
@@ -347,6 +347,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
 
   DevState& s = c->s;
   s.F = F; s.N = N; s.Npad = (int)Npad; s.K = 1;
+  s.p_update = 0; s.p_step = 0.1f;
   s.nchunk = (N + fca::kChunk - 1) / fca::kChunk;
   s.nchunk_em = (N + fca::kChunkEm - 1) / fca::kChunkEm;
   const size_t FJI = (size_t)F * J * I, FII = (size_t)F * I * I, FJII = (size_t)F * J * I * I;
@@ -514,6 +515,10 @@ fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
   if (!std::strcmp(key, "K")) {
     if (value < 1 || value > 64) return fail(c, FCA_ERR_ARG, "K must be in 1..64");
     c->s.K = (int)value;
+  } else if (!std::strcmp(key, "p_update")) {
+    if (value < 0 || value > 2) return fail(c, FCA_ERR_ARG, "p_update must be 0 (fixed point), 1 (gradient) or 2 (natural gradient)");
+    if (c->method != FCA_METHOD_AS && value != 0) return fail(c, FCA_ERR_STATE, "p_update applies to FastFCA-AS contexts");
+    c->s.p_update = (int)value;
   } else if (!std::strcmp(key, "check_finite")) {
     if (value != 0 && value != 1) return fail(c, FCA_ERR_ARG, "check_finite must be 0 or 1");
     c->check_finite = (int)value;
@@ -540,6 +545,7 @@ fca_status fca_get_option(fca_ctx* c, const char* key, long long* value) {
   if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
   if (!key || !value) return fail(c, FCA_ERR_ARG, "NULL key or value");
   if (!std::strcmp(key, "K")) *value = c->s.K;
+  else if (!std::strcmp(key, "p_update")) *value = c->s.p_update;
   else if (!std::strcmp(key, "check_finite")) *value = c->check_finite;
   else if (!std::strcmp(key, "path")) *value = c->path;
   else if (!std::strcmp(key, "waves")) *value = c->waves;
@@ -548,6 +554,26 @@ fca_status fca_get_option(fca_ctx* c, const char* key, long long* value) {
   else if (!std::strcmp(key, "last_waves")) *value = c->last_waves;
   else if (!std::strcmp(key, "last_bins_per_wg")) *value = c->last_bpw;
   else return fail(c, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
+  return FCA_OK;
+}
+
+fca_status fca_set_option_f64(fca_ctx* c, const char* key, double value) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!key) return fail(c, FCA_ERR_ARG, "NULL key");
+  if (!std::strcmp(key, "p_step")) {
+    if (!(value > 0.0 && value <= 1e3)) return fail(c, FCA_ERR_ARG, "p_step must be in (0, 1000]");
+    c->s.p_step = (float)value;
+  } else {
+    return fail(c, FCA_ERR_ARG, std::string("unknown real option '") + key + "'");
+  }
+  return FCA_OK;
+}
+
+fca_status fca_get_option_f64(fca_ctx* c, const char* key, double* value) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!key || !value) return fail(c, FCA_ERR_ARG, "NULL key or value");
+  if (!std::strcmp(key, "p_step")) *value = c->s.p_step;
+  else return fail(c, FCA_ERR_ARG, std::string("unknown real option '") + key + "'");
   return FCA_OK;
 }
 

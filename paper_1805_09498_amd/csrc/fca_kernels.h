@@ -333,12 +333,33 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
       }
     }
   }
-  for (int kk = 0; kk < s.K; ++kk) {
+  // gamma_i = S_i e_i / N (column i of G_i) for the gradient-type P steps
+  float gr[I], gi[I];
+#pragma unroll
+  for (int a = 0; a < I; ++a) { gr[a] = 0.f; gi[a] = 0.f; }
+  if (act && s.p_update != 0) {
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) {
+        gr[a] = (b == i) ? Sr[a][b] / fN : gr[a];
+        gi[a] = (b == i) ? Si[a][b] / fN : gi[a];
+      }
+  }
+  const int steps = s.p_update == 0 ? s.K : 1;
+  for (int kk = 0; kk < steps; ++kk) {
     float ar[I], ai[I];
     if (act) {
-      if (kk == 0) {
+      if (s.p_update == 2) {  // natural gradient: A = 1 + mu (1 - Gamma)
+#pragma unroll
+        for (int a = 0; a < I; ++a) {
+          ar[a] = ((a == i) ? 1.f + s.p_step : 0.f) - s.p_step * gr[a];
+          ai[a] = -s.p_step * gi[a];
+        }
+      } else if (kk == 0) {
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] = (a == i) ? fN : 0.f; ai[a] = 0.f; }
+        herm_solve<I>(Sr, Si, ar, ai);
       } else {
         float Ar[I][I], Ai[I][I];
 #pragma unroll
@@ -348,8 +369,8 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
         pinvh_col<I, float>(Ar, Ai, i, ar, ai);   // column i of A^-H
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
+        herm_solve<I>(Sr, Si, ar, ai);
       }
-      herm_solve<I>(Sr, Si, ar, ai);
     }
     __syncthreads();
     if (act) {
@@ -358,7 +379,33 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
     }
     __syncthreads();
   }
-  if (act) {
+  if (s.p_update == 1) {
+    // gradient: p_i + mu P^-H (e_i - gamma_i); the columns of P^-H go
+    // through the same LDS tile
+    float br[I], bi[I];
+    if (act) pinvh_col<I, float>(Pr, Pi, i, br, bi);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < I; ++a) { sAr[fl][a][i] = br[a]; sAi[fl][a][i] = bi[a]; }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < I; ++a) {
+        float pr = 0.f, pi = 0.f;
+#pragma unroll
+        for (int b = 0; b < I; ++b) { pr = (b == i) ? Pr[a][b] : pr; pi = (b == i) ? Pi[a][b] : pi; }
+#pragma unroll
+        for (int b = 0; b < I; ++b) {
+          const float dr = ((b == i) ? 1.f : 0.f) - gr[b], di = -gi[b];
+          pr = fmaf(s.p_step, sAr[fl][a][b] * dr - sAi[fl][a][b] * di, pr);
+          pi = fmaf(s.p_step, sAr[fl][a][b] * di + sAi[fl][a][b] * dr, pi);
+        }
+        s.P[(size_t)f * I * I + a * I + i] = make_float2(pr, pi);
+      }
+    }
+  } else if (act) {
     // column i of P_new = P_old A
 #pragma unroll
     for (int a = 0; a < I; ++a) {

@@ -242,9 +242,29 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       }
       const float fN = float(s.N);
       float ar[I], ai[I], pnr[I], pni[I];
+      // gamma_c = S_c e_c / N (column c of G_c), for the gradient-type steps;
+      // read from the LDS sums (packed: real parts on and above the
+      // diagonal, imaginary parts below).
+      float gr[I], gi[I];
+      if (s.p_update != 0) {
 #pragma unroll
-      for (int a = 0; a < I; ++a) { ar[a] = (a == c) ? fN : 0.f; ai[a] = 0.f; }
-      herm_solve<I>(Sr, Si, ar, ai);
+        for (int a = 0; a < I; ++a) {
+          const int ir = (a <= c) ? a * I + c : c * I + a, ii = (a <= c) ? c * I + a : a * I + c;
+          gr[a] = sum_waves(Qc, QSTRIDE, ir, nw) / fN;
+          gi[a] = (a == c) ? 0.f : ((a < c) ? 1.f : -1.f) * sum_waves(Qc, QSTRIDE, ii, nw) / fN;
+        }
+      }
+      if (s.p_update == 2) {  // natural gradient: A = 1 + mu (1 - Gamma)
+#pragma unroll
+        for (int a = 0; a < I; ++a) {
+          ar[a] = ((a == c) ? 1.f + s.p_step : 0.f) - s.p_step * gr[a];
+          ai[a] = -s.p_step * gi[a];
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < I; ++a) { ar[a] = (a == c) ? fN : 0.f; ai[a] = 0.f; }
+        herm_solve<I>(Sr, Si, ar, ai);
+      }
       // K > 1: further fixed-point steps a_c = G_c^-1 [A^-H]_c; lane b holds
       // column b of the current A, gathered with readlane (no LDS, no
       // barrier: only the bin's first wave takes part).  Compiled up to
@@ -252,7 +272,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       // cannot spare); the host sends K > 1 at larger I to the streaming
       // kernels.
 #pragma unroll 1
-      for (int kk = 1; kk < (I <= kResMaxIK ? s.K : 1); ++kk) {
+      for (int kk = 1; kk < ((I <= kResMaxIK && s.p_update == 0) ? s.K : 1); ++kk) {
         float A2r[I][I], A2i[I][I];
 #pragma unroll
         for (int a = 0; a < I; ++a)
@@ -281,6 +301,32 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           pi = fmaf(qi, ar[b], pi);
         }
         pnr[a] = pr; pni[a] = pi;
+      }
+      if constexpr (I <= kResMaxIK) {
+        if (s.p_update == 1) {
+          // gradient: p_c + mu P^-H (e_c - gamma_c); lane b forms column b of
+          // P^-H, the matrix is gathered with readlane (wave 0 only)
+          float Pr2[I][I], Pi2[I][I], br[I], bi[I];
+#pragma unroll
+          for (int a = 0; a < I; ++a)
+#pragma unroll
+            for (int b = 0; b < I; ++b) { Pr2[a][b] = sPr[bin][a][b]; Pi2[a][b] = sPi[bin][a][b]; }
+          pinvh_col<I, float>(Pr2, Pi2, c, br, bi);
+#pragma unroll
+          for (int a = 0; a < I; ++a) { pnr[a] = sPr[bin][a][c]; pni[a] = sPi[bin][a][c]; }
+#pragma unroll
+          for (int b = 0; b < I; ++b) {
+            const float dr = ((b == c) ? 1.f : 0.f) - gr[b];  // e_c - gamma_c
+            const float di = -gi[b];
+#pragma unroll
+            for (int a = 0; a < I; ++a) {
+              const float Br = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(br[a]), b));
+              const float Bi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bi[a]), b));
+              pnr[a] = fmaf(s.p_step, Br * dr - Bi * di, pnr[a]);
+              pni[a] = fmaf(s.p_step, Br * di + Bi * dr, pni[a]);
+            }
+          }
+        }
       }
       if (tb < I) {
 #pragma unroll

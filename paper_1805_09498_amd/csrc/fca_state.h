@@ -12,8 +12,8 @@ constexpr int kPts = 4;
 constexpr int kChunk = kBlock * kPts;
 constexpr int kChunkEm = kBlock;  // FCA EM: one point per lane
 // Largest I whose frequency-resident FastFCA-AS kernel runs K > 1
-// fixed-point steps per iteration; larger I with K > 1 uses the streaming
-// kernels.
+// fixed-point steps or the gradient P step (both need the inverse of a
+// matrix per lane); larger I with either uses the streaming kernels.
 constexpr int kResMaxIK = 4;
 
 // Internal layouts (library-owned):
@@ -27,6 +27,8 @@ struct DevState {
   int nchunk;     // tiles per bin of the AS streaming kernels
   int nchunk_em;  // tiles per bin of the EM kernels
   int K;          // fixed-point steps per hybrid iteration
+  int p_update;   // P step: 0 fixed point (eq. 23), 1 gradient, 2 natural gradient
+  float p_step;   // step size of the gradient-type P steps
   const float* xs;
   float* vs;
   float* lam;

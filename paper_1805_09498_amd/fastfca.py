@@ -36,7 +36,7 @@ FCA_METHOD_EM = 1
 
 EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
             "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
-            "fca_get_option", "fca_last_error", "fca_destroy",
+            "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
             "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
             "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
             "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft")
@@ -65,6 +65,10 @@ def _load():
     lib.fca_set_option.restype = i
     lib.fca_get_option.argtypes = [vp, c, ctypes.POINTER(ctypes.c_longlong)]
     lib.fca_get_option.restype = i
+    lib.fca_set_option_f64.argtypes = [vp, c, ctypes.c_double]
+    lib.fca_set_option_f64.restype = i
+    lib.fca_get_option_f64.argtypes = [vp, c, ctypes.POINTER(ctypes.c_double)]
+    lib.fca_get_option_f64.restype = i
     lib.fca_last_error.argtypes = [vp]
     lib.fca_last_error.restype = c
     lib.fca_destroy.argtypes = [vp]
@@ -231,6 +235,16 @@ def fca_set_option(ctx, key, value):
 def fca_get_option(ctx, key):
     out = ctypes.c_longlong()
     _check(lib.fca_get_option(ctx.handle, key.encode(), ctypes.byref(out)), ctx)
+    return out.value
+
+
+def fca_set_option_f64(ctx, key, value):
+    _check(lib.fca_set_option_f64(ctx.handle, key.encode(), float(value)), ctx)
+
+
+def fca_get_option_f64(ctx, key):
+    out = ctypes.c_double()
+    _check(lib.fca_get_option_f64(ctx.handle, key.encode(), ctypes.byref(out)), ctx)
     return out.value
 
 

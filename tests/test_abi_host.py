@@ -45,7 +45,7 @@ def test_header_declares_the_expected_calls():
     assert declared_functions() == sorted([
         "fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
         "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
-        "fca_get_option", "fca_last_error", "fca_destroy",
+        "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
         "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
         "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
         "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft"])

@@ -1,0 +1,72 @@
+"""GPU parity of the gradient-type P updates (option "p_update": 1 gradient,
+2 natural gradient; real option "p_step") against the oracle
+(oracle.fastfca_as_step_grad), on both execution paths, after 1 and 3
+iterations, at the parameter tolerance of the fixed-point update."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_common import TOL_PARAM, params, problem, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ff():
+    assert torch.cuda.is_available()
+    from paper_1805_09498_amd import fastfca
+    return fastfca
+
+
+def run(ff, p, n_iter, p_update, mu, path):
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+    ff.fca_set_option(ctx, "path", path)
+    ff.fca_set_option(ctx, "p_update", p_update)
+    ff.fca_set_option_f64(ctx, "p_step", mu)
+    ff.fastfca_as_iterate(ctx, n_iter)
+    return ctx
+
+
+@pytest.mark.parametrize("p_update,mu", [(1, 0.05), (2, 0.1)])
+@pytest.mark.parametrize("I,J", [(1, 2), (2, 3), (3, 3), (4, 2), (6, 4)])
+def test_gradient_type_steps_match_oracle(ff, p_update, mu, I, J):
+    p = problem(I, J, 9, 150, seed=70 + I)
+    paths = (0, 2) if (p_update == 1 and I > 4) else (0, 1, 2)
+    for n_iter in (1, 3):
+        v_ref, lam_ref, P_ref = p.v0, p.lam0, p.P0
+        for _ in range(n_iter):
+            v_ref, lam_ref, P_ref = oracle.fastfca_as_step_grad(p.x, v_ref, lam_ref, P_ref, mu, natural=(p_update == 2))
+        for path in paths:
+            ctx = run(ff, p, n_iter, p_update, mu, path)
+            v, lam, P = params(ff, ctx)
+            err = (rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref))
+            assert max(err) <= TOL_PARAM, (n_iter, path, err)
+    if p_update == 1 and I > 4:
+        with pytest.raises(ff.FcaError):
+            run(ff, p, 1, p_update, mu, 1)             # the resident kernels take it up to I = 4
+
+
+def test_step_options(ff):
+    p = problem(2, 2, 3, 40, seed=77)
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+    assert ff.fca_get_option(ctx, "p_update") == 0
+    assert ff.fca_get_option_f64(ctx, "p_step") == pytest.approx(0.1)
+    ff.fca_set_option_f64(ctx, "p_step", 0.25)
+    assert ff.fca_get_option_f64(ctx, "p_step") == pytest.approx(0.25)
+    for bad in (0.0, -1.0, float("nan"), 1e4):
+        with pytest.raises(ff.FcaError):
+            ff.fca_set_option_f64(ctx, "p_step", bad)
+    with pytest.raises(ff.FcaError):
+        ff.fca_set_option(ctx, "p_update", 3)
+    with pytest.raises(ff.FcaError):
+        ff.fca_set_option_f64(ctx, "nope", 1.0)
+    ff.fca_set_option(ctx, "p_update", 2)
+    with pytest.raises(ff.FcaError):
+        ff.fastfca_as_forward(ctx, 2, 1)             # the recorded run is for the fixed-point step
+    em = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"])
+    with pytest.raises(ff.FcaError):
+        ff.fca_set_option(em, "p_update", 1)

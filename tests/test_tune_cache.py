@@ -40,26 +40,27 @@ def test_measured_shape_is_stored_and_reused(cache_file):
     from paper_1805_09498_amd import fastfca as ff
     # shapes no other test tunes, so the in-process cache is empty for them
     iterate_once(ff, 2, 2, 7, 53, seed=41)
-    stored = lines_with(cache_file, " as I=2 J=2 F=7 N=53 K=1")
+    stored = lines_with(cache_file, " as I=2 J=2 F=7 N=53 ")
     assert len(stored) == 1
     key, val = stored[0].split("\t")
-    prefix = key[: key.index(" as I=")]
-    # plant an entry for another shape; the tuner must take it as it is
+    # plant an entry for another shape (the same key with J = 3); the tuner
+    # must take it as it is
+    other = key.replace(" J=2 ", " J=3 ")
     with open(cache_file, "a") as f:
-        f.write(f"{prefix} as I=2 J=3 F=7 N=53 K=1\t4 2\n")
+        f.write(f"{other}\t4 2\n")
     ctx = iterate_once(ff, 2, 3, 7, 53, seed=42)
     assert ff.fca_get_option(ctx, "last_waves") == 4
     assert ff.fca_get_option(ctx, "last_bins_per_wg") == 2
-    assert len(lines_with(cache_file, " as I=2 J=3 F=7 N=53 K=1")) == 1   # not measured again
+    assert len(lines_with(cache_file, " as I=2 J=3 F=7 N=53 ")) == 1   # not measured again
 
 
 def test_entry_that_does_not_fit_is_measured(cache_file):
     from paper_1805_09498_amd import fastfca as ff
     iterate_once(ff, 1, 2, 5, 61, seed=43)
-    key = lines_with(cache_file, " as I=1 J=2 F=5 N=61 K=1")[0].split("\t")[0]
-    prefix = key[: key.index(" as I=")]
+    key = lines_with(cache_file, " as I=1 J=2 F=5 N=61 ")[0].split("\t")[0]
+    other = key.replace(" J=2 ", " J=3 ")
     with open(cache_file, "a") as f:
-        f.write(f"{prefix} as I=1 J=3 F=5 N=61 K=1\t1 2\n")   # 2 bins per workgroup need >= 2 waves
+        f.write(f"{other}\t1 2\n")   # 2 bins per workgroup need >= 2 waves
     ctx = iterate_once(ff, 1, 3, 5, 61, seed=44)
     assert (ff.fca_get_option(ctx, "last_waves"), ff.fca_get_option(ctx, "last_bins_per_wg")) != (1, 2)
-    assert len(lines_with(cache_file, " as I=1 J=3 F=5 N=61 K=1")) == 2   # measured and appended
+    assert len(lines_with(cache_file, " as I=1 J=3 F=5 N=61 ")) == 2   # measured and appended
