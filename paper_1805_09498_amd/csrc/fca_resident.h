@@ -36,14 +36,24 @@ constexpr int kResMaxWaves = kResMaxBlock / kWave;
 template <int I>
 constexpr bool kResXInRegs = (I <= 4);
 
-// Sum of the per-wave partials part[w * stride + k] over the nw waves (the
-// loop is unrolled to the maximum wave count; nw is uniform).
-__device__ __forceinline__ float sum_waves(const float* part, int stride, int k, int nw) {
-  float t = part[k];
+// use(k, t_k) for k < V, t_k the sum of the per-wave partials
+// part[w * stride + k] over the nw waves (nw in {1, 2, 4}, uniform), summed in
+// wave order.  One uniform test selects the wave count for all V values (a
+// test per value costs a branch each), and each total is consumed as it is
+// formed, so no array of V totals stays live.
+template <int V, typename Use>
+__device__ __forceinline__ void sum_waves(const float* part, int stride, int nw, Use&& use) {
+  if (nw == 1) {
 #pragma unroll
-  for (int w = 1; w < kResMaxWaves; ++w)
-    if (w < nw) t += part[w * stride + k];
-  return t;
+    for (int k = 0; k < V; ++k) use(k, part[k]);
+  } else if (nw == 2) {
+#pragma unroll
+    for (int k = 0; k < V; ++k) use(k, part[k] + part[stride + k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      use(k, ((part[k] + part[stride + k]) + part[2 * stride + k]) + part[3 * stride + k]);
+  }
 }
 
 // The body of one frequency-resident workgroup: bins f0 .. f0 + nb - 1 of the
@@ -159,11 +169,10 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       wave_totals_to_lds<J * I>(flat, redS, VS);  // slot of wave `wave`
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-      for (int i = 0; i < I; ++i)  // eq. 20: old lambda times the scaled sum
-        lam[j][i] = sum_waves(binS, VS, j * I + i, nw) * (float(I) * lam[j][i] * invN);
+    // eq. 20: old lambda times the scaled sum
+    sum_waves<J * I>(binS, VS, nw, [&](int k, float t) {
+      lam[k / I][k % I] = t * (float(I) * lam[k / I][k % I] * invN);
+    });
 
     // ---- phase B: the weighted sums N G_i of y y^H (eq. 23) ----------------
     if constexpr (kOnePass) {
@@ -222,15 +231,14 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
     // straight to the barrier that publishes the new P.
     if (wl == 0) {
       // S_c = N G_c (upper triangle); column c of A solves S_c a = N e_c.
+      // packed: real parts on and above, imaginary parts below the diagonal
       float Sr[I][I], Si[I][I];
-      const float* Qc = binQ + (kOnePass ? c * I * I : c * VQ);
+      sum_waves<I * I>(binQ + (kOnePass ? c * I * I : c * VQ), QSTRIDE, nw, [&](int k, float t) {
+        const int a = k / I, b = k % I;
+        if (b >= a) Sr[a][b] = t; else Si[b][a] = t;
+      });
 #pragma unroll
-      for (int a = 0; a < I; ++a)
-#pragma unroll
-        for (int b = a; b < I; ++b) {
-          Sr[a][b] = sum_waves(Qc, QSTRIDE, a * I + b, nw);
-          Si[a][b] = (b > a) ? sum_waves(Qc, QSTRIDE, b * I + a, nw) : 0.f;
-        }
+      for (int a = 0; a < I; ++a) Si[a][a] = 0.f;
       if constexpr (kTrace) {
         if (tb < I) {  // S_c packed: real parts on and above, imaginary parts below the diagonal
           float* dst = tr.S + (size_t)it * tr.sstride + ((size_t)f * I + c) * I * I;
@@ -242,16 +250,19 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       }
       const float fN = float(s.N);
       float ar[I], ai[I], pnr[I], pni[I];
-      // gamma_c = S_c e_c / N (column c of G_c), for the gradient-type steps;
-      // read from the LDS sums (packed: real parts on and above the
-      // diagonal, imaginary parts below).
+      // gamma_c = S_c e_c / N (column c of G_c), for the gradient-type steps
       float gr[I], gi[I];
       if (s.p_update != 0) {
 #pragma unroll
         for (int a = 0; a < I; ++a) {
-          const int ir = (a <= c) ? a * I + c : c * I + a, ii = (a <= c) ? c * I + a : a * I + c;
-          gr[a] = sum_waves(Qc, QSTRIDE, ir, nw) / fN;
-          gi[a] = (a == c) ? 0.f : ((a < c) ? 1.f : -1.f) * sum_waves(Qc, QSTRIDE, ii, nw) / fN;
+          float r = 0.f, m = 0.f;  // a select chain keeps every index a constant
+#pragma unroll
+          for (int cc = 0; cc < I; ++cc) {  // entry (a, cc) of S_c: conj of (cc, a) below the diagonal
+            r = (c == cc) ? ((a <= cc) ? Sr[a][cc] : Sr[cc][a]) : r;
+            m = (c == cc) ? ((a == cc) ? 0.f : (a < cc) ? Si[a][cc] : -Si[cc][a]) : m;
+          }
+          gr[a] = r * invN;
+          gi[a] = m * invN;
         }
       }
       if (s.p_update == 2) {  // natural gradient: A = 1 + mu (1 - Gamma)
@@ -451,15 +462,15 @@ __global__ __launch_bounds__(kResMaxBlock) void k_em_resident(DevState s, int n_
     if (wbase == 0 && threadIdx.x < J) {
       const int j = threadIdx.x;
       float Rr[I][I], Ri[I][I], Xr[I][I], Xi[I][I];
+      sum_waves<I * I>(red + j * I * I, V, nw, [&](int k, float t) {
+        const int a = k / I, b = k % I;
+        if (b >= a) Rr[a][b] = t * invN; else Ri[b][a] = t * invN;
+      });
 #pragma unroll
       for (int a = 0; a < I; ++a) {
-        Rr[a][a] = sum_waves(red, V, j * I * I + a * I + a, nw) * invN; Ri[a][a] = 0.f;
+        Ri[a][a] = 0.f;
 #pragma unroll
-        for (int b = a + 1; b < I; ++b) {
-          Rr[a][b] = sum_waves(red, V, j * I * I + a * I + b, nw) * invN;
-          Ri[a][b] = sum_waves(red, V, j * I * I + b * I + a, nw) * invN;
-          Rr[b][a] = Rr[a][b]; Ri[b][a] = -Ri[a][b];
-        }
+        for (int b = a + 1; b < I; ++b) { Rr[b][a] = Rr[a][b]; Ri[b][a] = -Ri[a][b]; }
       }
       herm_inv<I>(Rr, Ri, Xr, Xi);
 #pragma unroll
@@ -492,7 +503,7 @@ int em_resident_fits(int N, int waves) {
   if constexpr (!em_resident_ok<I, J>()) {
     return 0;
   } else {
-    if (waves < 1 || waves > kResMaxWaves) return 0;
+    if (waves != 1 && waves != 2 && waves != 4) return 0;
     return N <= 8 * waves * kWave ? 1 : 0;
   }
 }
@@ -525,7 +536,7 @@ constexpr int res_max_npt() {
 
 template <int I, int J>
 int as_resident_fits(int N, int waves, int bpw) {
-  if (waves < 1 || waves > kResMaxWaves) return 0;
+  if (waves != 1 && waves != 2 && waves != 4) return 0;
   if (bpw != 1 && bpw != 2) return 0;
   if (bpw == 2 && waves < 2) return 0;
   return N <= res_max_npt<I, J>() * (waves / bpw) * kWave ? 1 : 0;
