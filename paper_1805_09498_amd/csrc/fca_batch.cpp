@@ -68,9 +68,12 @@ hipError_t launch_group(fca_batch* b, const Group& g, int waves, int n_iter) {
       }
     return hipSuccess;
   }
+  bool general = false;  // any member with K > 1 or another P update
+  for (int m : g.members) general = general || b->ctx[m]->s.K > 1 || b->ctx[m]->s.p_update != 0;
   for (int done = 0; done < n_iter;) {
     const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
-    hipError_t e = g.ks->as_batch_resident(g.d_states, g.d_tiles, g.ntiles, g.n_max, b->stream, step, waves);
+    hipError_t e =
+        g.ks->as_batch_resident(g.d_states, g.d_tiles, g.ntiles, g.n_max, b->stream, step, waves, general);
     if (e != hipSuccess) return e;
     done += step;
   }

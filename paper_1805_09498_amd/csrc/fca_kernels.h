@@ -61,39 +61,38 @@ __device__ __forceinline__ void as_transform(const float (&Pr)[I][I], const floa
 // E-step statistics and v update of one point, in a form with fewer
 // operations that is algebraically identical to eq. 16-17, 19 and 20:
 //   d_i = sum_j v_j lambda_ji,   g_ji = v_j lambda_ji / d_i  (diagonal Wiener gain),
-//   |mu~_ji|^2 + phi~_ji = g_ji u_ji  with  u_ji = g_ji |y_i|^2 + d_i - v_j lambda_ji
-//                                            = d_i + v_j lambda_ji (|y_i|^2 / d_i - 1),
-//   v_j <- (1/I) sum_i g_ji u_ji / lambda_ji = (v_j / I) U_j,  U_j = sum_i u_ji / d_i  (eq. 19),
-//   summand of eq. 20:  g_ji u_ji / v_j(new) = I lambda_ji (u_ji / d_i) / U_j.
-// The point adds (u_ji / d_i) / U_j to S_ji and updates v (when `take`); the
-// caller applies the factor I lambda_ji / N once per bin after summing over
-// the frames.
+//   (|mu~_ji|^2 + phi~_ji) / (v_j lambda_ji) = 1 - g_ji + g_ji |y_i|^2 / d_i
+//                                            = 1 + v_j lambda_ji e_i =: r_ji,
+//   with e_i = (|y_i|^2 / d_i - 1) / d_i;
+//   v_j <- (1/I) sum_i v_j r_ji = v_j W_j,  W_j = 1 + (v_j / I) sum_i lambda_ji e_i  (eq. 19),
+//   summand of eq. 20:  (|mu~|^2 + phi~)_ji / v_j(new) = lambda_ji r_ji / W_j.
+// The point adds r_ji / W_j to S_ji and updates v (when `take`); the caller
+// applies the factor lambda_ji / N once per bin after summing over the frames.
 template <int I, int J>
 __device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&lam)[J][I],
                                             float (&v)[J], float (&S)[J][I], bool take) {
-  float ut[J][I];
+  float e[I];
 #pragma unroll
   for (int i = 0; i < I; ++i) {
-    float vl[J];
-    float d = 0.f;
+    float d = v[0] * lam[0][i];
 #pragma unroll
-    for (int j = 0; j < J; ++j) { vl[j] = v[j] * lam[j][i]; d += vl[j]; }
+    for (int j = 1; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
     const float t = rcp(d);
-    const float h = fmaf(y2[i], t, -1.0f);
-#pragma unroll
-    for (int j = 0; j < J; ++j) ut[j][i] = fmaf(vl[j], h, d) * t;
+    e[i] = fmaf(y2[i], t, -1.0f) * t;
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    float U = ut[j][0];
+    float le[I];
+    float u = 0.f;
 #pragma unroll
-    for (int i = 1; i < I; ++i) U += ut[j][i];
+    for (int i = 0; i < I; ++i) { le[i] = lam[j][i] * e[i]; u += le[i]; }
+    const float W = fmaf(v[j] * (1.0f / float(I)), u, 1.0f);
     // A lane that does not own a frame (take = false) keeps its v, so that
     // padded lanes stay finite over any number of iterations.
-    v[j] = take ? v[j] * U * (1.0f / float(I)) : v[j];
-    const float rU = take ? rcp(U) : 0.f;
+    const float rW = take ? rcp(W) : 0.f;
 #pragma unroll
-    for (int i = 0; i < I; ++i) S[j][i] = fmaf(ut[j][i], rU, S[j][i]);
+    for (int i = 0; i < I; ++i) S[j][i] = fmaf(fmaf(v[j], le[i], 1.0f), rW, S[j][i]);
+    v[j] = take ? v[j] * W : v[j];
   }
 }
 
@@ -235,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
   for (int t = threadIdx.x; t < J * I; t += kBlock) {
     float acc = 0.f;
     for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
-    sLam[t] = acc * (float(I) * s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
+    sLam[t] = acc * (s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
   }
   __syncthreads();
   float lam[J][I];
@@ -312,7 +311,7 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
       float acc = 0.f;
       for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + j * I + i];
       float* l = s.lam + (size_t)f * J * I + j * I + i;
-      *l = acc * (float(I) * (*l) * invN);  // eq. 20 (old lambda times the scaled sum)
+      *l = acc * ((*l) * invN);  // eq. 20 (old lambda times the scaled sum)
     }
     // S_i from the tile partials.
     float A[I * I];

@@ -57,10 +57,14 @@ __device__ __forceinline__ void sum_waves(const float* part, int stride, int nw,
 }
 
 // The body of one frequency-resident workgroup: bins f0 .. f0 + nb - 1 of the
-// problem s (nb in {1, 2}), n_iter hybrid iterations.
-template <int I, int J, int NPT, bool kTrace = false>
+// problem s (nb in {1, 2}), n_iter hybrid iterations.  kGen = false compiles
+// the plain step only (K = 1, fixed-point P update), which keeps the
+// registers and branches of the other P updates off the common path.
+template <int I, int J, int NPT, bool kTrace = false, bool kGen = true>
 __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int nb, int n_iter,
                                                  const Trace& tr = Trace{}) {
+  const int p_update = kGen ? s.p_update : 0;
+  const int n_fp = kGen ? s.K : 1;  // fixed-point steps per iteration
   constexpr int VS = pad4(J * I);
   constexpr bool kOnePass = I * I * I <= 64;       // all I weighted sums in one sweep
   constexpr int VQ = kOnePass ? pad4(I * I * I) : pad4(I * I);
@@ -96,6 +100,9 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
   float* vf = s.vs + (size_t)f * J * s.Npad;
   float xr[kXReg ? NPT : 1][I], xi[kXReg ? NPT : 1][I], v[NPT][J];
   float yr[NPT][I], yi[NPT][I];  // y = P^H x of the current iteration (phase A -> B)
+  // |y_i|^2 is kept for phase B as well where the registers allow
+  constexpr bool kKeepY2 = kOnePass && NPT <= 8 && !kGen;
+  float y2k[kKeepY2 ? NPT : 1][I];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tb + k * T;
@@ -158,6 +165,10 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           float y2[I];
 #pragma unroll
           for (int i = 0; i < I; ++i) y2[i] = fmaf(yr[k][i], yr[k][i], yi[k][i] * yi[k][i]);
+          if constexpr (kKeepY2) {
+#pragma unroll
+            for (int i = 0; i < I; ++i) y2k[k][i] = y2[i];
+          }
           as_point_em<I, J>(y2, lam, v[k], S, ok);
         }
       }
@@ -171,7 +182,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
     __syncthreads();
     // eq. 20: old lambda times the scaled sum
     sum_waves<J * I>(binS, VS, nw, [&](int k, float t) {
-      lam[k / I][k % I] = t * (float(I) * lam[k / I][k % I] * invN);
+      lam[k / I][k % I] = t * (lam[k / I][k % I] * invN);
     });
 
     // ---- phase B: the weighted sums N G_i of y y^H (eq. 23) ----------------
@@ -189,6 +200,10 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           float w[I], z[I * I];
           as_point_weights<I, J>(lam, v[k], w);
           herm_outer<I>(z, yr[k], yi[k]);
+          if constexpr (kKeepY2) {
+#pragma unroll
+            for (int a = 0; a < I; ++a) z[a * I + a] = y2k[k][a];
+          }
 #pragma unroll
           for (int i = 0; i < I; ++i)
 #pragma unroll
@@ -252,7 +267,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       float ar[I], ai[I], pnr[I], pni[I];
       // gamma_c = S_c e_c / N (column c of G_c), for the gradient-type steps
       float gr[I], gi[I];
-      if (s.p_update != 0) {
+      if (p_update != 0) {
 #pragma unroll
         for (int a = 0; a < I; ++a) {
           float r = 0.f, m = 0.f;  // a select chain keeps every index a constant
@@ -265,7 +280,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           gi[a] = m * invN;
         }
       }
-      if (s.p_update == 2) {  // natural gradient: A = 1 + mu (1 - Gamma)
+      if (p_update == 2) {  // natural gradient: A = 1 + mu (1 - Gamma)
 #pragma unroll
         for (int a = 0; a < I; ++a) {
           ar[a] = ((a == c) ? 1.f + s.p_step : 0.f) - s.p_step * gr[a];
@@ -283,7 +298,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       // cannot spare); the host sends K > 1 at larger I to the streaming
       // kernels.
 #pragma unroll 1
-      for (int kk = 1; kk < ((I <= kResMaxIK && s.p_update == 0) ? s.K : 1); ++kk) {
+      for (int kk = 1; kk < ((I <= kResMaxIK && p_update == 0) ? n_fp : 1); ++kk) {
         float A2r[I][I], A2i[I][I];
 #pragma unroll
         for (int a = 0; a < I; ++a)
@@ -314,7 +329,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
         pnr[a] = pr; pni[a] = pi;
       }
       if constexpr (I <= kResMaxIK) {
-        if (s.p_update == 1) {
+        if (p_update == 1) {
           // gradient: p_c + mu P^-H (e_c - gamma_c); lane b forms column b of
           // P^-H, the matrix is gathered with readlane (wave 0 only)
           float Pr2[I][I], Pi2[I][I], br[I], bi[I];
@@ -377,31 +392,32 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 }
 
 // One problem: workgroup g owns bins g*bpw .. (the last may own fewer).
-template <int I, int J, int NPT>
+template <int I, int J, int NPT, bool kGen>
 __global__ __launch_bounds__(kResMaxBlock) void k_as_resident(DevState s, int n_iter, int bpw) {
   const int f0 = blockIdx.x * bpw;
   const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
-  as_resident_body<I, J, NPT>(s, f0, nb, n_iter);
+  as_resident_body<I, J, NPT, false, kGen>(s, f0, nb, n_iter);
 }
 
-// The same as k_as_resident, recording the state after every iteration.
+// The same as k_as_resident (plain step only), recording the state after
+// every iteration.
 template <int I, int J, int NPT>
 __global__ __launch_bounds__(kResMaxBlock) void k_as_resident_trace(DevState s, int n_iter, int bpw, Trace tr) {
   const int f0 = blockIdx.x * bpw;
   const int nb = (s.F - f0 < bpw) ? (s.F - f0) : bpw;
-  as_resident_body<I, J, NPT, true>(s, f0, nb, n_iter, tr);
+  as_resident_body<I, J, NPT, true, false>(s, f0, nb, n_iter, tr);
 }
 
 // Many problems of the same (I, J): workgroup g takes tile g = (problem,
 // bin) of a table the host sorts by decreasing N, so the hardware dispatcher
 // hands the longest tiles out first.
-template <int I, int J, int NPT>
+template <int I, int J, int NPT, bool kGen>
 __global__ __launch_bounds__(kResMaxBlock) void k_as_resident_batch(const DevState* __restrict__ states,
                                                                     const int2* __restrict__ tiles,
                                                                     int n_iter) {
   const int2 t = tiles[blockIdx.x];
   const DevState s = states[t.x];
-  as_resident_body<I, J, NPT>(s, t.y, 1, n_iter);
+  as_resident_body<I, J, NPT, false, kGen>(s, t.y, 1, n_iter);
 }
 
 // Frequency-resident conventional FCA EM (Section 3.3), the same execution
@@ -543,23 +559,53 @@ int as_resident_fits(int N, int waves, int bpw) {
 }
 
 // Batched launch: tiles of problems whose N are at most n_max, one workgroup
-// of `waves` waves per tile.
-template <int I, int J>
-hipError_t launch_as_batch_resident(const DevState* states, const int2* tiles, int ntiles, int n_max,
-                                    hipStream_t st, int n_iter, int waves) {
+// of `waves` waves per tile; `general` when any member takes K > 1 or another
+// P update.
+template <int I, int J, bool kGen>
+hipError_t launch_as_batch_g(const DevState* states, const int2* tiles, int ntiles, int n_max, hipStream_t st,
+                             int n_iter, int waves) {
   const int T = waves * kWave;
   const int need = (n_max + T - 1) / T;
   constexpr int mx = res_max_npt<I, J>();
   dim3 grid(ntiles), block(T);
   if (ntiles <= 0) return hipSuccess;
   if (need <= 4)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, 4>), grid, block, 0, st, states, tiles, n_iter);
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, 4, kGen>), grid, block, 0, st, states, tiles, n_iter);
   else if (need <= 8 && mx >= 8)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, states, tiles, n_iter);
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 8 ? 8 : 4), kGen>), grid, block, 0, st, states, tiles,
+                       n_iter);
   else if (need <= 12 && mx >= 12)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, states, tiles, n_iter);
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 12 ? 12 : 4), kGen>), grid, block, 0, st, states, tiles,
+                       n_iter);
   else if (need <= 16 && mx >= 16)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, states, tiles, n_iter);
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 16 ? 16 : 4), kGen>), grid, block, 0, st, states, tiles,
+                       n_iter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int I, int J>
+hipError_t launch_as_batch_resident(const DevState* states, const int2* tiles, int ntiles, int n_max,
+                                    hipStream_t st, int n_iter, int waves, bool general) {
+  return general ? launch_as_batch_g<I, J, true>(states, tiles, ntiles, n_max, st, n_iter, waves)
+                 : launch_as_batch_g<I, J, false>(states, tiles, ntiles, n_max, st, n_iter, waves);
+}
+
+template <int I, int J, bool kGen>
+hipError_t launch_as_resident_g(const DevState& s, hipStream_t st, int n_iter, int waves, int bpw) {
+  const int T = (waves / bpw) * kWave;  // lanes per bin when the workgroup is full
+  const int need = (s.N + T - 1) / T;
+  constexpr int mx = res_max_npt<I, J>();
+  dim3 grid((s.F + bpw - 1) / bpw), block(waves * kWave);
+  if (need <= 4)
+    hipLaunchKernelGGL((k_as_resident<I, J, 4, kGen>), grid, block, 0, st, s, n_iter, bpw);
+  else if (need <= 8 && mx >= 8)
+    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 8 ? 8 : 4), kGen>), grid, block, 0, st, s, n_iter, bpw);
+  else if (need <= 12 && mx >= 12)
+    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 12 ? 12 : 4), kGen>), grid, block, 0, st, s, n_iter, bpw);
+  else if (need <= 16 && mx >= 16)
+    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 16 ? 16 : 4), kGen>), grid, block, 0, st, s, n_iter, bpw);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -567,26 +613,15 @@ hipError_t launch_as_batch_resident(const DevState* states, const int2* tiles, i
 
 template <int I, int J>
 hipError_t launch_as_iter_resident(const DevState& s, hipStream_t st, int n_iter, int waves, int bpw) {
-  const int T = (waves / bpw) * kWave;  // lanes per bin when the workgroup is full
-  const int need = (s.N + T - 1) / T;
-  constexpr int mx = res_max_npt<I, J>();
-  dim3 grid((s.F + bpw - 1) / bpw), block(waves * kWave);
-  if (need <= 4)
-    hipLaunchKernelGGL((k_as_resident<I, J, 4>), grid, block, 0, st, s, n_iter, bpw);
-  else if (need <= 8 && mx >= 8)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, s, n_iter, bpw);
-  else if (need <= 12 && mx >= 12)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 12 ? 12 : 4)>), grid, block, 0, st, s, n_iter, bpw);
-  else if (need <= 16 && mx >= 16)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 16 ? 16 : 4)>), grid, block, 0, st, s, n_iter, bpw);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  return (s.K > 1 || s.p_update != 0) ? launch_as_resident_g<I, J, true>(s, st, n_iter, waves, bpw)
+                                      : launch_as_resident_g<I, J, false>(s, st, n_iter, waves, bpw);
 }
 
+// The recording kernel runs the plain step only (K = 1, fixed-point P update).
 template <int I, int J>
 hipError_t launch_as_iter_resident_trace(const DevState& s, hipStream_t st, int n_iter, int waves, int bpw,
                                          const Trace& tr) {
+  if (s.K != 1 || s.p_update != 0) return hipErrorInvalidValue;
   const int T = (waves / bpw) * kWave;
   const int need = (s.N + T - 1) / T;
   constexpr int mx = res_max_npt<I, J>();

@@ -83,7 +83,7 @@ struct KernelSet {
   hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves, int bpw);
   int (*as_resident_fits)(int N, int waves, int bpw);
   hipError_t (*as_batch_resident)(const DevState* states, const int2* tiles, int ntiles, int n_max,
-                                  hipStream_t, int n_iter, int waves);
+                                  hipStream_t, int n_iter, int waves, bool general);
   hipError_t (*em_iter)(const DevState&, hipStream_t);
   hipError_t (*em_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
   int (*em_resident_fits)(int N, int waves);
