@@ -142,27 +142,6 @@ __device__ __forceinline__ void herm_rank1_acc(float (&A)[I * I], float w, const
   }
 }
 
-// ----------------------------------------------------------------------------
-// Block reduction of per-lane partial sums into a global vector.
-// ----------------------------------------------------------------------------
-template <int V>
-__device__ inline void block_sum_store(float (&a)[V], float* __restrict__ out, float* lds) {
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-#pragma unroll
-  for (int k = 0; k < V; ++k) {
-    const float t = wave_sum(a[k]);
-    if (lane == 0) lds[wave * V + k] = t;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < V; k += blockDim.x) {
-    float t = 0.f;
-    for (int w = 0; w < nw; ++w) t += lds[w * V + k];
-    out[k] = t;
-  }
-  __syncthreads();
-}
-
 // Load the bin's P into registers from a staged copy.
 template <int I>
 __device__ __forceinline__ void load_P(const float2* __restrict__ Pg, float (&Pr)[I][I], float (&Pi)[I][I]) {
@@ -178,21 +157,73 @@ __device__ __forceinline__ void load_P(const float2* __restrict__ Pg, float (&Pr
 // ----------------------------------------------------------------------------
 // FastFCA-AS streaming kernels.
 // ----------------------------------------------------------------------------
+// Tiles are (bin, chunk of kChunk frames): lane t of a 256-lane workgroup
+// takes frames chunk*kChunk + p*256 + t, p < kPts.  Up to I = 4 the bin's P
+// sits in registers; above, every lane reads it from LDS for each frame (a
+// broadcast read), which keeps the registers for more waves per SIMD.
+template <int I>
+constexpr bool kStreamPinLds = (I >= 5);
+
+// y = P^H x with P read from LDS (row-major, split re/im).
+template <int I>
+__device__ __forceinline__ void as_transform_lds(const float* sPr, const float* sPi, const float (&xr)[I],
+                                                 const float (&xi)[I], float (&yr)[I], float (&yi)[I]) {
+#pragma unroll
+  for (int i = 0; i < I; ++i) {
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      const float pr = sPr[k * I + i], pi = sPi[k * I + i];
+      a = fmaf(pr, xr[k], a);
+      a = fmaf(pi, xi[k], a);
+      b = fmaf(pr, xi[k], b);
+      b = fmaf(-pi, xr[k], b);
+    }
+    yr[i] = a; yi[i] = b;
+  }
+}
+
+// Per-workgroup totals of V per-lane values: transposed wave sums, then the
+// waves' totals summed in wave order by the first V lanes, stored to out.
+template <int V>
+__device__ __forceinline__ void block_totals_store(const float (&a)[V], float* __restrict__ out, float* lds) {
+  constexpr int V4 = pad4(V);
+  wave_totals_to_lds<V>(a, lds, V4);
+  __syncthreads();
+  const int nw = blockDim.x / kWave;
+  for (int k = threadIdx.x; k < V; k += blockDim.x) {
+    float t = lds[k];
+    for (int w = 1; w < nw; ++w) t += lds[w * V4 + k];
+    out[k] = t;
+  }
+}
+
+// Pass A: y = P^H x, E-step and v update per frame (eq. 15-19, the form of
+// as_point_em), and the tile's sums of the eq. 20 summands.
 template <int I, int J>
 __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
   const int f = blockIdx.y, chunk = blockIdx.x;
-  __shared__ float2 sP[I * I];
+  __shared__ float sPr[I * I], sPi[I * I];
   __shared__ float sLam[J * I];
-  __shared__ float red[(kBlock / kWave) * J * I];
-  for (int t = threadIdx.x; t < I * I; t += kBlock) sP[t] = s.P[(size_t)f * I * I + t];
+  __shared__ float red[(kBlock / kWave) * pad4(J * I)];
+  for (int t = threadIdx.x; t < I * I; t += kBlock) {
+    const float2 q = s.P[(size_t)f * I * I + t];
+    sPr[t] = q.x; sPi[t] = q.y;
+  }
   for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
   __syncthreads();
-  float Pr[I][I], Pi[I][I], lam[J][I];
-  load_P<I>(sP, Pr, Pi);
+  float lam[J][I];
 #pragma unroll
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+  float Pr[kStreamPinLds<I> ? 1 : I][kStreamPinLds<I> ? 1 : I], Pi[kStreamPinLds<I> ? 1 : I][kStreamPinLds<I> ? 1 : I];
+  if constexpr (!kStreamPinLds<I>) {
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) { Pr[a][b] = sPr[a * I + b]; Pi[a][b] = sPi[a * I + b]; }
+  }
   float S[J][I];
 #pragma unroll
   for (int j = 0; j < J; ++j)
@@ -201,18 +232,29 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
 
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   float* vf = s.vs + (size_t)f * J * s.Npad;
-#pragma unroll
+#pragma unroll kStreamPinLds<I> ? 1 : kPts
   for (int p = 0; p < kPts; ++p) {
     const int n = chunk * kChunk + p * kBlock + threadIdx.x;
-    if (n < s.N) {
-      float xr[I], xi[I], v[J];
+    const bool ok = n < s.N;
+    const int nn = ok ? n : 0;  // frames past N read frame 0 and add nothing
+    float xr[I], xi[I], v[J], yr[I], yi[I], y2[I];
 #pragma unroll
-      for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+    for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
 #pragma unroll
-      for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
-      float y2[I];
-      as_transform_pow<I>(Pr, Pi, xr, xi, y2);
-      as_point_em<I, J>(y2, lam, v, S, true);
+    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
+    if constexpr (kStreamPinLds<I>) {
+      // an offset opaque to the optimiser keeps P's reads inside the loop
+      // (hoisted, they would hold all of P in registers)
+      int zo = 0;
+      asm volatile("" : "+s"(zo));
+      as_transform_lds<I>(sPr + zo, sPi + zo, xr, xi, yr, yi);
+    } else {
+      as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) y2[i] = fmaf(yr[i], yr[i], yi[i] * yi[i]);
+    as_point_em<I, J>(y2, lam, v, S, ok);
+    if (ok) {
 #pragma unroll
       for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[j];
     }
@@ -222,64 +264,171 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int i = 0; i < I; ++i) flat[j * I + i] = S[j][i];
-  block_sum_store<J * I>(flat, s.partA + ((size_t)f * s.nchunk + chunk) * J * I, red);
+  block_totals_store<J * I>(flat, s.partA + ((size_t)f * s.nchunk + chunk) * J * I, red);
 }
+
+// Pass B: lambda (eq. 20) from the tile sums of pass A, then the tile's
+// weighted sums of eq. 23 in the basis of y: for every column c,
+// sum_n w_c y y^H with w_c = 1 / sum_j v_j lambda_jc, stored packed (slot
+// (a, b), a <= b: Re, slot (b, a), a < b: Im) at partB[tile][c][I*I].
+//
+// Up to I = 4 a lane accumulates all I^3 sums of its own frames.  Above, the
+// I^3 sums per frame exceed the registers, so the tile is staged in LDS: each
+// lane writes its frame's w (I values) and y y^H (I^2 values) as one record,
+// then lane (g, a) of group g accumulates row a of the packed y y^H times
+// every w_c over the frames g, g + G, ... of the stage (I^2 sums per lane, I
+// lanes per frame), and the groups' sums are added at the end of the tile.
+template <int I>
+struct PassBLayout {
+  static constexpr bool kLds = I >= 5;
+  static constexpr int kRec = I * I + I;                // y y^H, then w
+  static constexpr int kStride = kRec | 1;              // odd record stride (LDS banks)
+  static constexpr int kGroups = kBlock / I;            // frames accumulated side by side
+  static constexpr int kFloats = kLds ? kBlock * kStride : 1;
+  static_assert(!kLds || kGroups * I * I * I <= kBlock * kStride, "group sums reuse the records");
+};
 
 template <int I, int J>
 __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
+  using L = PassBLayout<I>;
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float sLam[J * I];
-  __shared__ float red[(kBlock / kWave) * I * I];
+  __shared__ float sPr[I * I], sPi[I * I];
+  __shared__ float sRec[L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
   const float invN = 1.0f / float(s.N);
   for (int t = threadIdx.x; t < J * I; t += kBlock) {
     float acc = 0.f;
     for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
     sLam[t] = acc * (s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
   }
+  for (int t = threadIdx.x; t < I * I; t += kBlock) {
+    const float2 q = s.P[(size_t)f * I * I + t];  // the old P (k_as_solve replaces it after this pass)
+    sPr[t] = q.x; sPi[t] = q.y;
+  }
   __syncthreads();
-  float lam[J][I];
-#pragma unroll
-  for (int j = 0; j < J; ++j)
-#pragma unroll
-    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
-
-  // the old P (k_as_solve replaces it after this pass)
-  float Pr[I][I], Pi[I][I];
-#pragma unroll
-  for (int a = 0; a < I; ++a)
-#pragma unroll
-    for (int b = 0; b < I; ++b) {
-      const float2 t = s.P[(size_t)f * I * I + a * I + b];
-      Pr[a][b] = t.x; Pi[a][b] = t.y;
-    }
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   const float* vf = s.vs + (size_t)f * J * s.Npad;
-  float yr[kPts][I], yi[kPts][I], w[kPts][I];
-#pragma unroll
-  for (int p = 0; p < kPts; ++p) {
+  float* out = s.partB + ((size_t)f * s.nchunk + chunk) * I * I * I;
+
+  // frame n of this lane: y, the weights w (0 past N) and y y^H (packed)
+  auto frame = [&](int p, const float (&lam)[J][I], float (&w)[I], float (&z)[I * I]) {
     const int n = chunk * kChunk + p * kBlock + threadIdx.x;
     const bool ok = n < s.N;
     const int nn = ok ? n : 0;
-    float v[J], xr[I], xi[I];
+    float xr[I], xi[I], v[J], yr[I], yi[I];
 #pragma unroll
     for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
-    as_transform<I>(Pr, Pi, xr, xi, yr[p], yi[p]);
 #pragma unroll
     for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
-    float wp[I];
-    as_point_weights<I, J>(lam, v, wp);
+    int zo = 0;  // opaque offset: P is read from LDS per frame, not hoisted into registers
+    asm volatile("" : "+s"(zo));
+    as_transform_lds<I>(sPr + zo, sPi + zo, xr, xi, yr, yi);
+    as_point_weights<I, J>(lam, v, w);
 #pragma unroll
-    for (int i = 0; i < I; ++i) w[p][i] = ok ? wp[i] : 0.f;
-  }
-  float* out = s.partB + ((size_t)f * s.nchunk + chunk) * I * I * I;
+    for (int i = 0; i < I; ++i) w[i] = ok ? w[i] : 0.f;
+    herm_outer<I>(z, yr, yi);
+  };
+
+  if constexpr (!L::kLds) {
+    float lam[J][I];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+    float A[I][I * I];
+#pragma unroll
+    for (int c = 0; c < I; ++c)
+#pragma unroll
+      for (int q = 0; q < I * I; ++q) A[c][q] = 0.f;
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) {
+      float w[I], z[I * I];
+      frame(p, lam, w, z);
+#pragma unroll
+      for (int c = 0; c < I; ++c)
+#pragma unroll
+        for (int q = 0; q < I * I; ++q) A[c][q] = fmaf(w[c], z[q], A[c][q]);
+    }
+    float flat[I * I * I];
+#pragma unroll
+    for (int c = 0; c < I; ++c)
+#pragma unroll
+      for (int q = 0; q < I * I; ++q) flat[c * I * I + q] = A[c][q];
+    block_totals_store<I * I * I>(flat, out, sRec);
+  } else {
+    const int a = threadIdx.x % I, g = threadIdx.x / I;  // row a of group g (g >= kGroups: idle)
+    float acc[I][I];                                     // [c][b]: row a, column b of S_c (packed)
+#pragma unroll
+    for (int c = 0; c < I; ++c)
+#pragma unroll
+      for (int b = 0; b < I; ++b) acc[c][b] = 0.f;
 #pragma unroll 1
-  for (int i = 0; i < I; ++i) {
-    float A[I * I];
+    for (int p = 0; p < kPts; ++p) {
+      {
+        // this lane's record: y y^H and w, each value stored as it is formed;
+        // lambda is read from LDS (in registers it would sit beside the sums)
+        const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+        const bool ok = n < s.N;
+        const int nn = ok ? n : 0;
+        int zo = 0;
+        asm volatile("" : "+s"(zo));
+        float xr[I], xi[I], yr[I], yi[I];
 #pragma unroll
-    for (int k = 0; k < I * I; ++k) A[k] = 0.f;
+        for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
+        as_transform_lds<I>(sPr + zo, sPi + zo, xr, xi, yr, yi);
+        float* rec = sRec + threadIdx.x * L::kStride;
 #pragma unroll
-    for (int p = 0; p < kPts; ++p) herm_rank1_acc<I>(A, w[p][i], yr[p], yi[p]);
-    block_sum_store<I * I>(A, out + i * I * I, red);
+        for (int a2 = 0; a2 < I; ++a2) {
+          rec[a2 * I + a2] = fmaf(yr[a2], yr[a2], yi[a2] * yi[a2]);
+#pragma unroll
+          for (int b = a2 + 1; b < I; ++b) {
+            rec[a2 * I + b] = fmaf(yr[a2], yr[b], yi[a2] * yi[b]);
+            rec[b * I + a2] = fmaf(yi[a2], yr[b], -yr[a2] * yi[b]);
+          }
+        }
+        float v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
+        const float* lamz = sLam + zo;
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+          float d = v[0] * lamz[c];
+#pragma unroll
+          for (int j = 1; j < J; ++j) d = fmaf(v[j], lamz[j * I + c], d);
+          rec[I * I + c] = ok ? rcp(d) : 0.f;
+        }
+      }
+      __syncthreads();
+      if (g < L::kGroups) {
+#pragma unroll 2
+        for (int m = g; m < kBlock; m += L::kGroups) {
+          const float* rec = sRec + m * L::kStride;
+          float w[I], z[I];
+#pragma unroll
+          for (int c = 0; c < I; ++c) w[c] = rec[I * I + c];
+#pragma unroll
+          for (int b = 0; b < I; ++b) z[b] = rec[a * I + b];
+#pragma unroll
+          for (int c = 0; c < I; ++c)
+#pragma unroll
+            for (int b = 0; b < I; ++b) acc[c][b] = fmaf(w[c], z[b], acc[c][b]);
+        }
+      }
+      __syncthreads();  // the records are rewritten by the next stage
+    }
+    // the groups' sums, added in group order
+    if (g < L::kGroups) {
+#pragma unroll
+      for (int c = 0; c < I; ++c)
+#pragma unroll
+        for (int b = 0; b < I; ++b) sRec[g * I * I * I + c * I * I + a * I + b] = acc[c][b];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < I * I * I; o += kBlock) {
+      float t = sRec[o];
+      for (int gg = 1; gg < L::kGroups; ++gg) t += sRec[gg * I * I * I + o];
+      out[o] = t;
+    }
   }
 }
 
