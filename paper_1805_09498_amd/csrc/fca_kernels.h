@@ -164,20 +164,43 @@ __device__ __forceinline__ void load_P(const float2* __restrict__ Pg, float (&Pr
 template <int I>
 constexpr bool kStreamPinLds = (I >= 5);
 
-// y = P^H x with P read from LDS (row-major, split re/im).
+// P staged in LDS by columns: entry i * PH + h holds P[2h][i] and
+// P[2h + 1][i] (re, im, re, im; zero past I), so that y_i = (P^H x)_i reads
+// column i with 128-bit broadcast loads.
 template <int I>
-__device__ __forceinline__ void as_transform_lds(const float* sPr, const float* sPi, const float (&xr)[I],
-                                                 const float (&xi)[I], float (&yr)[I], float (&yi)[I]) {
+constexpr int kPH = (I + 1) / 2;
+
+template <int I>
+__device__ __forceinline__ void stage_P_columns(const float2* __restrict__ P, float4* sPt) {
+  for (int t = threadIdx.x; t < I * kPH<I>; t += blockDim.x) {
+    const int i = t / kPH<I>, k = 2 * (t % kPH<I>);
+    const float2 p0 = P[k * I + i];
+    const float2 p1 = (k + 1 < I) ? P[(k + 1) * I + i] : make_float2(0.f, 0.f);
+    sPt[t] = make_float4(p0.x, p0.y, p1.x, p1.y);
+  }
+}
+
+// y = P^H x with P read from its column staging in LDS.
+template <int I>
+__device__ __forceinline__ void as_transform_lds(const float4* sPt, const float (&xr)[I], const float (&xi)[I],
+                                                 float (&yr)[I], float (&yi)[I]) {
 #pragma unroll
   for (int i = 0; i < I; ++i) {
     float a = 0.f, b = 0.f;
 #pragma unroll
-    for (int k = 0; k < I; ++k) {
-      const float pr = sPr[k * I + i], pi = sPi[k * I + i];
-      a = fmaf(pr, xr[k], a);
-      a = fmaf(pi, xi[k], a);
-      b = fmaf(pr, xi[k], b);
-      b = fmaf(-pi, xr[k], b);
+    for (int h = 0; h < kPH<I>; ++h) {
+      const float4 q = sPt[i * kPH<I> + h];
+      const int k = 2 * h;
+      a = fmaf(q.x, xr[k], a);
+      a = fmaf(q.y, xi[k], a);
+      b = fmaf(q.x, xi[k], b);
+      b = fmaf(-q.y, xr[k], b);
+      if (k + 1 < I) {
+        a = fmaf(q.z, xr[k + 1], a);
+        a = fmaf(q.w, xi[k + 1], a);
+        b = fmaf(q.z, xi[k + 1], b);
+        b = fmaf(-q.w, xr[k + 1], b);
+      }
     }
     yr[i] = a; yi[i] = b;
   }
@@ -203,13 +226,10 @@ __device__ __forceinline__ void block_totals_store(const float (&a)[V], float* _
 template <int I, int J>
 __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
   const int f = blockIdx.y, chunk = blockIdx.x;
-  __shared__ float sPr[I * I], sPi[I * I];
+  __shared__ float4 sPt[I * kPH<I>];
   __shared__ float sLam[J * I];
   __shared__ float red[(kBlock / kWave) * pad4(J * I)];
-  for (int t = threadIdx.x; t < I * I; t += kBlock) {
-    const float2 q = s.P[(size_t)f * I * I + t];
-    sPr[t] = q.x; sPi[t] = q.y;
-  }
+  stage_P_columns<I>(s.P + (size_t)f * I * I, sPt);
   for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
   __syncthreads();
   float lam[J][I];
@@ -220,9 +240,13 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
   float Pr[kStreamPinLds<I> ? 1 : I][kStreamPinLds<I> ? 1 : I], Pi[kStreamPinLds<I> ? 1 : I][kStreamPinLds<I> ? 1 : I];
   if constexpr (!kStreamPinLds<I>) {
 #pragma unroll
-    for (int a = 0; a < I; ++a)
+    for (int i = 0; i < I; ++i)
 #pragma unroll
-      for (int b = 0; b < I; ++b) { Pr[a][b] = sPr[a * I + b]; Pi[a][b] = sPi[a * I + b]; }
+      for (int h = 0; h < kPH<I>; ++h) {
+        const float4 q = sPt[i * kPH<I> + h];
+        Pr[2 * h][i] = q.x; Pi[2 * h][i] = q.y;
+        if (2 * h + 1 < I) { Pr[2 * h + 1][i] = q.z; Pi[2 * h + 1][i] = q.w; }
+      }
   }
   float S[J][I];
 #pragma unroll
@@ -232,6 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
 
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   float* vf = s.vs + (size_t)f * J * s.Npad;
+  // (loading frame p + 1 ahead of frame p costs the registers of a third
+  // wave per SIMD at I = 8, and is slower there)
 #pragma unroll kStreamPinLds<I> ? 1 : kPts
   for (int p = 0; p < kPts; ++p) {
     const int n = chunk * kChunk + p * kBlock + threadIdx.x;
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
       // (hoisted, they would hold all of P in registers)
       int zo = 0;
       asm volatile("" : "+s"(zo));
-      as_transform_lds<I>(sPr + zo, sPi + zo, xr, xi, yr, yi);
+      as_transform_lds<I>(sPt + zo, xr, xi, yr, yi);
     } else {
       as_transform<I>(Pr, Pi, xr, xi, yr, yi);
     }
@@ -278,6 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
 // then lane (g, a) of group g accumulates row a of the packed y y^H times
 // every w_c over the frames g, g + G, ... of the stage (I^2 sums per lane, I
 // lanes per frame), and the groups' sums are added at the end of the tile.
+// A record keeps slot (a, b) of y y^H at position b * I + a, so that the I
+// lanes of a group read consecutive words, and its stride is odd, so that
+// the lanes writing records (one each) and the groups reading them fall on
+// different LDS banks.
 template <int I>
 struct PassBLayout {
   static constexpr bool kLds = I >= 5;
@@ -293,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
   using L = PassBLayout<I>;
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float sLam[J * I];
-  __shared__ float sPr[I * I], sPi[I * I];
+  __shared__ float4 sPt[I * kPH<I>];
   __shared__ float sRec[L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
   const float invN = 1.0f / float(s.N);
   for (int t = threadIdx.x; t < J * I; t += kBlock) {
@@ -301,10 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
     for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
     sLam[t] = acc * (s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
   }
-  for (int t = threadIdx.x; t < I * I; t += kBlock) {
-    const float2 q = s.P[(size_t)f * I * I + t];  // the old P (k_as_solve replaces it after this pass)
-    sPr[t] = q.x; sPi[t] = q.y;
-  }
+  stage_P_columns<I>(s.P + (size_t)f * I * I, sPt);  // the old P (k_as_solve replaces it after this pass)
   __syncthreads();
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   const float* vf = s.vs + (size_t)f * J * s.Npad;
@@ -322,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
     for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
     int zo = 0;  // opaque offset: P is read from LDS per frame, not hoisted into registers
     asm volatile("" : "+s"(zo));
-    as_transform_lds<I>(sPr + zo, sPi + zo, xr, xi, yr, yi);
+    as_transform_lds<I>(sPt + zo, xr, xi, yr, yi);
     as_point_weights<I, J>(lam, v, w);
 #pragma unroll
     for (int i = 0; i < I; ++i) w[i] = ok ? w[i] : 0.f;
@@ -362,33 +389,45 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
     for (int c = 0; c < I; ++c)
 #pragma unroll
       for (int b = 0; b < I; ++b) acc[c][b] = 0.f;
-#pragma unroll 1
+    // Every stage's frame is loaded up front: the LDS records already limit
+    // the workgroups per CU, so the registers are free to keep more loads in
+    // flight.
+    float xr_[kPts][I], xi_[kPts][I], v_[kPts][J];
+#pragma unroll
     for (int p = 0; p < kPts; ++p) {
+      const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+      const int nn = n < s.N ? n : 0;  // frames past N read frame 0 (weight 0)
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        xr_[p][i] = xf[(size_t)i * s.Npad + nn];
+        xi_[p][i] = xf[(size_t)(I + i) * s.Npad + nn];
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) v_[p][j] = vf[(size_t)j * s.Npad + nn];
+    }
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) {
+      const float (&xr)[I] = xr_[p];
+      const float (&xi)[I] = xi_[p];
+      const float (&v)[J] = v_[p];
       {
         // this lane's record: y y^H and w, each value stored as it is formed;
         // lambda is read from LDS (in registers it would sit beside the sums)
-        const int n = chunk * kChunk + p * kBlock + threadIdx.x;
-        const bool ok = n < s.N;
-        const int nn = ok ? n : 0;
+        const bool ok = chunk * kChunk + p * kBlock + (int)threadIdx.x < s.N;
         int zo = 0;
         asm volatile("" : "+s"(zo));
-        float xr[I], xi[I], yr[I], yi[I];
-#pragma unroll
-        for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
-        as_transform_lds<I>(sPr + zo, sPi + zo, xr, xi, yr, yi);
+        float yr[I], yi[I];
+        as_transform_lds<I>(sPt + zo, xr, xi, yr, yi);
         float* rec = sRec + threadIdx.x * L::kStride;
 #pragma unroll
         for (int a2 = 0; a2 < I; ++a2) {
           rec[a2 * I + a2] = fmaf(yr[a2], yr[a2], yi[a2] * yi[a2]);
 #pragma unroll
-          for (int b = a2 + 1; b < I; ++b) {
-            rec[a2 * I + b] = fmaf(yr[a2], yr[b], yi[a2] * yi[b]);
-            rec[b * I + a2] = fmaf(yi[a2], yr[b], -yr[a2] * yi[b]);
+          for (int b = a2 + 1; b < I; ++b) {  // slot (a, b) at b * I + a (see below)
+            rec[b * I + a2] = fmaf(yr[a2], yr[b], yi[a2] * yi[b]);
+            rec[a2 * I + b] = fmaf(yi[a2], yr[b], -yr[a2] * yi[b]);
           }
         }
-        float v[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
         const float* lamz = sLam + zo;
 #pragma unroll
         for (int c = 0; c < I; ++c) {
@@ -407,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
 #pragma unroll
           for (int c = 0; c < I; ++c) w[c] = rec[I * I + c];
 #pragma unroll
-          for (int b = 0; b < I; ++b) z[b] = rec[a * I + b];
+          for (int b = 0; b < I; ++b) z[b] = rec[b * I + a];
 #pragma unroll
           for (int c = 0; c < I; ++c)
 #pragma unroll
