@@ -26,7 +26,10 @@
 
 namespace fca {
 
-constexpr int kAdjBlock = 256;
+// Two waves per bin: the adjoint kernels need ~250 VGPRs at I = J = 3 (two
+// waves per SIMD), so 4-wave workgroups fit two per CU and the 513th bin of
+// a 513-bin problem waited for a second round; 2-wave workgroups fit four.
+constexpr int kAdjBlock = 128;
 
 template <int I, int J>
 constexpr int adj_red_size() {
