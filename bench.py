@@ -58,7 +58,7 @@ def fca_em_flops_per_point_iter(I, J):
     return 2 * J * I * I + 4 * I ** 3 + J * (12 * I ** 3 + 20 * I * I)
 
 
-KERNEL_SOURCES = ("fca_resident.h", "fca_kernels.h", "fca_device.h", "fca_state.h")
+KERNEL_SOURCES = ("fca_resident.h", "fca_point.h", "fca_device.h", "fca_state.h")  # what k_as_resident compiles from
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_as_resident_speech10s_traffic.txt")
 
 

@@ -1,6 +1,7 @@
 // Instantiates every kernel of one (I, J) = (FCA_I, FCA_J) pair and exposes
 // its host launchers.  The build compiles one translation unit per pair.
 #include "fca_adjoint.h"
+#include "fca_em_resident.h"
 #include "fca_resident.h"
 
 #define FCA_CAT4_(a, b, c, d) a##b##c##d

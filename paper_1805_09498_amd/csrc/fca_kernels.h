@@ -13,146 +13,10 @@
 #pragma once
 
 #include "fca_device.h"
+#include "fca_point.h"
 #include "fca_state.h"
 
 namespace fca {
-
-// ----------------------------------------------------------------------------
-// Per-point arithmetic of FastFCA-AS.
-// ----------------------------------------------------------------------------
-
-// y = P^H x: y_i = sum_k conj(P_ki) x_k; returns |y_i|^2.
-template <int I>
-__device__ __forceinline__ void as_transform_pow(const float (&Pr)[I][I], const float (&Pi)[I][I],
-                                                 const float (&xr)[I], const float (&xi)[I],
-                                                 float (&y2)[I]) {
-#pragma unroll
-  for (int i = 0; i < I; ++i) {
-    float yr = 0.f, yi = 0.f;
-#pragma unroll
-    for (int k = 0; k < I; ++k) {
-      yr = fmaf(Pr[k][i], xr[k], yr);
-      yr = fmaf(Pi[k][i], xi[k], yr);
-      yi = fmaf(Pr[k][i], xi[k], yi);
-      yi = fmaf(-Pi[k][i], xr[k], yi);
-    }
-    y2[i] = fmaf(yr, yr, yi * yi);
-  }
-}
-
-template <int I>
-__device__ __forceinline__ void as_transform(const float (&Pr)[I][I], const float (&Pi)[I][I],
-                                             const float (&xr)[I], const float (&xi)[I],
-                                             float (&yr)[I], float (&yi)[I]) {
-#pragma unroll
-  for (int i = 0; i < I; ++i) {
-    float a = 0.f, b = 0.f;
-#pragma unroll
-    for (int k = 0; k < I; ++k) {
-      a = fmaf(Pr[k][i], xr[k], a);
-      a = fmaf(Pi[k][i], xi[k], a);
-      b = fmaf(Pr[k][i], xi[k], b);
-      b = fmaf(-Pi[k][i], xr[k], b);
-    }
-    yr[i] = a; yi[i] = b;
-  }
-}
-
-// E-step statistics and v update of one point, in a form with fewer
-// operations that is algebraically identical to eq. 16-17, 19 and 20:
-//   d_i = sum_j v_j lambda_ji,   g_ji = v_j lambda_ji / d_i  (diagonal Wiener gain),
-//   (|mu~_ji|^2 + phi~_ji) / (v_j lambda_ji) = 1 - g_ji + g_ji |y_i|^2 / d_i
-//                                            = 1 + v_j lambda_ji e_i =: r_ji,
-//   with e_i = (|y_i|^2 / d_i - 1) / d_i;
-//   v_j <- (1/I) sum_i v_j r_ji = v_j W_j,  W_j = 1 + (v_j / I) sum_i lambda_ji e_i  (eq. 19),
-//   summand of eq. 20:  (|mu~|^2 + phi~)_ji / v_j(new) = lambda_ji r_ji / W_j.
-// The point adds r_ji / W_j to S_ji and updates v (when `take`); the caller
-// applies the factor lambda_ji / N once per bin after summing over the frames.
-template <int I, int J>
-__device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&lam)[J][I],
-                                            float (&v)[J], float (&S)[J][I], bool take) {
-  float e[I];
-#pragma unroll
-  for (int i = 0; i < I; ++i) {
-    float d = v[0] * lam[0][i];
-#pragma unroll
-    for (int j = 1; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
-    const float t = rcp(d);
-    e[i] = fmaf(y2[i], t, -1.0f) * t;
-  }
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    float le[I];
-    float u = 0.f;
-#pragma unroll
-    for (int i = 0; i < I; ++i) { le[i] = lam[j][i] * e[i]; u += le[i]; }
-    const float W = fmaf(v[j] * (1.0f / float(I)), u, 1.0f);
-    // A lane that does not own a frame (take = false) keeps its v, so that
-    // padded lanes stay finite over any number of iterations.
-    const float rW = take ? rcp(W) : 0.f;
-#pragma unroll
-    for (int i = 0; i < I; ++i) S[j][i] = fmaf(fmaf(v[j], le[i], 1.0f), rW, S[j][i]);
-    v[j] = take ? v[j] * W : v[j];
-  }
-}
-
-// 1 / d_i with d_i = sum_j v_j lambda_ji (the weights of eq. 23).
-template <int I, int J>
-__device__ __forceinline__ void as_point_weights(const float (&lam)[J][I], const float (&v)[J],
-                                                 float (&w)[I]) {
-#pragma unroll
-  for (int i = 0; i < I; ++i) {
-    float d = 0.f;
-#pragma unroll
-    for (int j = 0; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
-    w[i] = rcp(d);
-  }
-}
-
-// Packed Hermitian slot layout of an I x I matrix in I*I reals: slot (a, b)
-// with a <= b holds Re A_ab, slot (b, a) with a < b holds Im A_ab.
-// Adds w * x x^H, i.e. A_ab += w x_a conj(x_b).
-// z = y y^H in the packed Hermitian layout of herm_rank1_acc.
-template <int I>
-__device__ __forceinline__ void herm_outer(float (&z)[I * I], const float (&yr)[I], const float (&yi)[I]) {
-#pragma unroll
-  for (int a = 0; a < I; ++a) {
-    z[a * I + a] = fmaf(yr[a], yr[a], yi[a] * yi[a]);
-#pragma unroll
-    for (int b = a + 1; b < I; ++b) {
-      z[a * I + b] = fmaf(yr[a], yr[b], yi[a] * yi[b]);
-      z[b * I + a] = fmaf(yi[a], yr[b], -yr[a] * yi[b]);
-    }
-  }
-}
-
-template <int I>
-__device__ __forceinline__ void herm_rank1_acc(float (&A)[I * I], float w, const float (&xr)[I],
-                                               const float (&xi)[I]) {
-#pragma unroll
-  for (int a = 0; a < I; ++a) {
-    A[a * I + a] = fmaf(w, fmaf(xr[a], xr[a], xi[a] * xi[a]), A[a * I + a]);
-#pragma unroll
-    for (int b = a + 1; b < I; ++b) {
-      const float zr = fmaf(xr[a], xr[b], xi[a] * xi[b]);
-      const float zi = fmaf(xi[a], xr[b], -xr[a] * xi[b]);
-      A[a * I + b] = fmaf(w, zr, A[a * I + b]);
-      A[b * I + a] = fmaf(w, zi, A[b * I + a]);
-    }
-  }
-}
-
-// Load the bin's P into registers from a staged copy.
-template <int I>
-__device__ __forceinline__ void load_P(const float2* __restrict__ Pg, float (&Pr)[I][I], float (&Pi)[I][I]) {
-#pragma unroll
-  for (int a = 0; a < I; ++a)
-#pragma unroll
-    for (int b = 0; b < I; ++b) {
-      const float2 t = Pg[a * I + b];
-      Pr[a][b] = t.x; Pi[a][b] = t.y;
-    }
-}
 
 // ----------------------------------------------------------------------------
 // FastFCA-AS streaming kernels.
@@ -311,22 +175,27 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
 template <int I>
 struct PassBLayout {
   static constexpr bool kLds = I >= 5;
+  // lanes = frames per stage: 2 waves, so that more workgroups share a CU
+  // and wait at their stage barriers independently
+  static constexpr int kThreads = kLds ? 128 : kBlock;
+  static constexpr int kStages = kChunk / kThreads;
   static constexpr int kRec = I * I + I;                // y y^H, then w
   static constexpr int kStride = kRec | 1;              // odd record stride (LDS banks)
-  static constexpr int kGroups = kBlock / I;            // frames accumulated side by side
-  static constexpr int kFloats = kLds ? kBlock * kStride : 1;
-  static_assert(!kLds || kGroups * I * I * I <= kBlock * kStride, "group sums reuse the records");
+  static constexpr int kGroups = kThreads / I;          // frames accumulated side by side
+  static constexpr int kFloats = kLds ? kThreads * kStride : 1;
+  static_assert(!kLds || kGroups * I * I * I <= kThreads * kStride, "group sums reuse the records");
+  static_assert(kChunk % kThreads == 0, "stages tile a chunk");
 };
 
 template <int I, int J>
-__global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
+__global__ __launch_bounds__(PassBLayout<I>::kThreads) void k_as_pass_b(DevState s) {
   using L = PassBLayout<I>;
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float sLam[J * I];
   __shared__ float4 sPt[I * kPH<I>];
   __shared__ float sRec[L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
   const float invN = 1.0f / float(s.N);
-  for (int t = threadIdx.x; t < J * I; t += kBlock) {
+  for (int t = threadIdx.x; t < J * I; t += L::kThreads) {
     float acc = 0.f;
     for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
     sLam[t] = acc * (s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
@@ -389,31 +258,31 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
     for (int c = 0; c < I; ++c)
 #pragma unroll
       for (int b = 0; b < I; ++b) acc[c][b] = 0.f;
-    // Every stage's frame is loaded up front: the LDS records already limit
-    // the workgroups per CU, so the registers are free to keep more loads in
-    // flight.
-    float xr_[kPts][I], xi_[kPts][I], v_[kPts][J];
-#pragma unroll
-    for (int p = 0; p < kPts; ++p) {
-      const int n = chunk * kChunk + p * kBlock + threadIdx.x;
+    // the frame of the next stage is loaded while this one is summed
+    float xr[I], xi[I], v[J], xrn[I], xin[I], vnx[J];
+    auto load = [&](int p) {
+      const int n = chunk * kChunk + p * L::kThreads + threadIdx.x;
       const int nn = n < s.N ? n : 0;  // frames past N read frame 0 (weight 0)
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        xr_[p][i] = xf[(size_t)i * s.Npad + nn];
-        xi_[p][i] = xf[(size_t)(I + i) * s.Npad + nn];
+        xrn[i] = xf[(size_t)i * s.Npad + nn];
+        xin[i] = xf[(size_t)(I + i) * s.Npad + nn];
       }
 #pragma unroll
-      for (int j = 0; j < J; ++j) v_[p][j] = vf[(size_t)j * s.Npad + nn];
-    }
+      for (int j = 0; j < J; ++j) vnx[j] = vf[(size_t)j * s.Npad + nn];
+    };
+    load(0);
+#pragma unroll 1
+    for (int p = 0; p < L::kStages; ++p) {
 #pragma unroll
-    for (int p = 0; p < kPts; ++p) {
-      const float (&xr)[I] = xr_[p];
-      const float (&xi)[I] = xi_[p];
-      const float (&v)[J] = v_[p];
+      for (int i = 0; i < I; ++i) { xr[i] = xrn[i]; xi[i] = xin[i]; }
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = vnx[j];
+      if (p + 1 < L::kStages) load(p + 1);
       {
         // this lane's record: y y^H and w, each value stored as it is formed;
         // lambda is read from LDS (in registers it would sit beside the sums)
-        const bool ok = chunk * kChunk + p * kBlock + (int)threadIdx.x < s.N;
+        const bool ok = chunk * kChunk + p * L::kThreads + (int)threadIdx.x < s.N;
         int zo = 0;
         asm volatile("" : "+s"(zo));
         float yr[I], yi[I];
@@ -440,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
       __syncthreads();
       if (g < L::kGroups) {
 #pragma unroll 2
-        for (int m = g; m < kBlock; m += L::kGroups) {
+        for (int m = g; m < L::kThreads; m += L::kGroups) {
           const float* rec = sRec + m * L::kStride;
           float w[I], z[I];
 #pragma unroll
@@ -463,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_b(DevState s) {
         for (int b = 0; b < I; ++b) sRec[g * I * I * I + c * I * I + a * I + b] = acc[c][b];
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < I * I * I; o += kBlock) {
+    for (int o = threadIdx.x; o < I * I * I; o += L::kThreads) {
       float t = sRec[o];
       for (int gg = 1; gg < L::kGroups; ++gg) t += sRec[gg * I * I * I + o];
       out[o] = t;
@@ -613,7 +482,7 @@ template <int I, int J>
 hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
   dim3 grid(s.nchunk, s.F);
   hipLaunchKernelGGL((k_as_pass_a<I, J>), grid, dim3(kBlock), 0, st, s);
-  hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(kBlock), 0, st, s);
+  hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
   hipLaunchKernelGGL((k_as_solve<I, J>), dim3((s.F + 7) / 8), dim3(64), 0, st, s);
   return hipGetLastError();
 }
