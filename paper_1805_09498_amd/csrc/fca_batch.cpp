@@ -35,8 +35,20 @@ thread_local std::string g_batch_init_error;
 
 }  // namespace
 
+// Groups run side by side on up to kLanes streams of their own (default
+// priority), forked from and joined back into the caller's stream, so that
+// the workgroups of one (I, J) group fill the CUs that another group's tail
+// leaves idle.  Under graph capture the fork and join become the graph's
+// dependencies.
+constexpr int kLanes = 3;  // with the caller's stream, the four hardware queues of a process
+
 struct fca_batch {
   hipStream_t stream;
+  int nlanes;                      // streams in use (1: everything on `stream`)
+  hipStream_t lane[kLanes];
+  hipEvent_t fork;
+  hipEvent_t join[kLanes];
+  std::vector<int> order;          // groups by decreasing estimated work
   std::vector<fca_ctx*> ctx;
   std::vector<Group> groups;
   void* dev;  // one allocation for all group tables
@@ -59,11 +71,11 @@ fca_status bhip(fca_batch* b, hipError_t e, const char* where) {
   return bfail(b, FCA_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-hipError_t launch_group(fca_batch* b, const Group& g, int waves, int n_iter) {
+hipError_t launch_group(fca_batch* b, const Group& g, int waves, int n_iter, hipStream_t st) {
   if (waves == 0) {
     for (int m : g.members)
       for (int it = 0; it < n_iter; ++it) {
-        hipError_t e = g.ks->as_iter_stream(b->ctx[m]->s, b->stream);
+        hipError_t e = g.ks->as_iter_stream(b->ctx[m]->s, st);
         if (e != hipSuccess) return e;
       }
     return hipSuccess;
@@ -73,7 +85,7 @@ hipError_t launch_group(fca_batch* b, const Group& g, int waves, int n_iter) {
   for (int done = 0; done < n_iter;) {
     const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
     hipError_t e =
-        g.ks->as_batch_resident(g.d_states, g.d_tiles, g.ntiles, g.n_max, b->stream, step, waves, general);
+        g.ks->as_batch_resident(g.d_states, g.d_tiles, g.ntiles, g.n_max, st, step, waves, general);
     if (e != hipSuccess) return e;
     done += step;
   }
@@ -125,7 +137,7 @@ fca_status tune(fca_batch* b) {
         for (int trial = 0; trial < 2 && e == hipSuccess; ++trial) {
           if ((e = save_restore(b, g, false)) != hipSuccess) break;
           if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) break;
-          if ((e = launch_group(b, g, w, len ? n1 + n2 : n1)) != hipSuccess) break;
+          if ((e = launch_group(b, g, w, len ? n1 + n2 : n1, b->stream)) != hipSuccess) break;
           if ((e = hipEventRecord(e1, b->stream)) != hipSuccess) break;
           if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
           float ms = 0.f;
@@ -150,11 +162,27 @@ fca_status tune(fca_batch* b) {
 }
 
 hipError_t launch_all(fca_batch* b, int n_iter) {
-  for (const Group& g : b->groups) {
-    hipError_t e = launch_group(b, g, g.waves, n_iter);
-    if (e != hipSuccess) return e;
+  if (b->nlanes <= 1) {
+    for (const Group& g : b->groups) {
+      hipError_t e = launch_group(b, g, g.waves, n_iter, b->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  return hipSuccess;
+  hipError_t e = hipEventRecord(b->fork, b->stream);
+  for (int k = 0; k < b->nlanes && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->lane[k], b->fork, 0);
+  // the largest groups first, dealt round-robin over the lanes
+  for (size_t r = 0; r < b->order.size() && e == hipSuccess; ++r) {
+    const Group& g = b->groups[b->order[r]];
+    e = launch_group(b, g, g.waves, n_iter, b->lane[r % b->nlanes]);
+  }
+  // join every lane, also after an error (a capture must end joined)
+  for (int k = 0; k < b->nlanes; ++k) {
+    hipError_t e2 = hipEventRecord(b->join[k], b->lane[k]);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(b->stream, b->join[k], 0);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
 }
 
 void drop_graphs(fca_batch* b) {
@@ -183,6 +211,9 @@ fca_status fca_batch_init(fca_batch** out, int n_mix, const int* F, const int* N
   fca_batch* b = new (std::nothrow) fca_batch();
   if (!b) return bfail(nullptr, FCA_ERR_HIP, "host allocation failed");
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  b->nlanes = 0;
+  b->fork = nullptr;
+  for (int k = 0; k < kLanes; ++k) { b->lane[k] = nullptr; b->join[k] = nullptr; }
   b->dev = nullptr;
   b->use_graph = 1;
   b->autotune = 1;
@@ -244,6 +275,27 @@ fca_status fca_batch_init(fca_batch** out, int n_mix, const int* F, const int* N
     if (e != hipSuccess) {
       fca_batch_destroy(b);
       return bhip(nullptr, e, "batch table upload");
+    }
+  }
+  // groups by decreasing work (tiles x frames x per-point cost), and the
+  // side streams
+  for (size_t k = 0; k < b->groups.size(); ++k) b->order.push_back((int)k);
+  auto work = [&](int k) {
+    const Group& g = b->groups[k];
+    return (double)g.ntiles * g.n_max * (double)g.I * (g.I * g.I + g.J);
+  };
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) { return work(a) > work(c); });
+  const int want = (int)std::min<size_t>(kLanes, b->groups.size());
+  if (want > 1) {
+    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int k = 0; k < want && e == hipSuccess; ++k) {
+      e = hipStreamCreateWithFlags(&b->lane[k], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+      if (e == hipSuccess) b->nlanes = k + 1;
+    }
+    if (e != hipSuccess) {
+      fca_batch_destroy(b);
+      return bhip(nullptr, e, "batch streams");
     }
   }
   *out = b;
@@ -344,6 +396,14 @@ const char* fca_batch_last_error(const fca_batch* b) { return b ? b->err.c_str()
 void fca_batch_destroy(fca_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (int k = 0; k < kLanes; ++k) {
+    if (b->lane[k]) {
+      (void)hipStreamSynchronize(b->lane[k]);
+      (void)hipStreamDestroy(b->lane[k]);
+    }
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   drop_graphs(b);
   for (fca_ctx* c : b->ctx) fca_destroy(c);
   if (b->dev) (void)hipFree(b->dev);
