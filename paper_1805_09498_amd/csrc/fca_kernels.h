@@ -547,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_as_loglik(DevState s) {
 
 // Per bin: sum of the tiles + N (2 ln|det P| - I ln pi).
 template <int I>
-__global__ void k_as_loglik_bin(DevState s) {
+__global__ __launch_bounds__(64) void k_as_loglik_bin(DevState s) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= s.F) return;
   float Mr[I][I], Mi[I][I];
@@ -576,7 +576,7 @@ hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // Bm[f] = P(f)^-H, one lane per (bin, column).
 template <int I>
-__global__ void k_p_inv_herm(DevState s) {
+__global__ __launch_bounds__(64) void k_p_inv_herm(DevState s) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int f = t / I, c = t % I;
   if (f >= s.F) return;
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(kBlock) void k_em_pass(DevState s) {
 // S_j <- (1/N) sum over tiles (eq. 10), exactly Hermitian; S_j^-1 for the next
 // v update.  One lane per (bin, source).
 template <int I, int J>
-__global__ void k_em_finalize(DevState s) {
+__global__ __launch_bounds__(64) void k_em_finalize(DevState s) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int f = t / J, j = t % J;
   if (f >= s.F) return;
@@ -867,7 +867,7 @@ hipError_t launch_em_iter(const DevState& s, hipStream_t st) {
 // S_j = P^-H diag(lambda_j) P^-1 (eq. 12) and S_j^-1 = P diag(1/lambda_j) P^H,
 // one lane per (bin, source): the EM starting point equal to an AS state.
 template <int I, int J>
-__global__ void k_em_from_as(DevState s) {
+__global__ __launch_bounds__(64) void k_em_from_as(DevState s) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int f = t / J, j = t % J;
   if (f >= s.F) return;
@@ -921,7 +921,7 @@ hipError_t launch_em_from_as(const DevState& s, hipStream_t st) {
 // S_j^-1 of caller-given S_j (its upper triangle; the stored S_j is made
 // exactly Hermitian from it).
 template <int I, int J>
-__global__ void k_em_rinv(DevState s) {
+__global__ __launch_bounds__(64) void k_em_rinv(DevState s) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int f = t / J, j = t % J;
   if (f >= s.F) return;
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_em_loglik(DevState s) {
 }
 
 template <int I>
-__global__ void k_em_loglik_bin(DevState s) {
+__global__ __launch_bounds__(64) void k_em_loglik_bin(DevState s) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= s.F) return;
   double acc = 0.0;

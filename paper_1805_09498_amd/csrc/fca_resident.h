@@ -36,6 +36,11 @@ constexpr int kResMaxWaves = kResMaxBlock / kWave;
 template <int I>
 constexpr bool kResXInRegs = (I <= 4);
 
+// Above I = 4 the eq. 23 sums of the resident kernel take several passes
+// over the points, CPP columns each (I^2 accumulators per column).
+template <int I>
+constexpr int kResColsPerPass = (I <= 6) ? 2 : 1;
+
 // use(k, t_k) for k < V, t_k the sum of the per-wave partials
 // part[w * stride + k] over the nw waves (nw in {1, 2, 4}, uniform), summed in
 // wave order.  One uniform test selects the wave count for all V values (a
@@ -217,22 +222,55 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
         for (int q = 0; q < I * I; ++q) flat[i * I * I + q] = A[i][q];
       wave_totals_to_lds<I * I * I>(flat, redQ, QSTRIDE);
     } else {
-      // one pass over the points per column i; the weight 1 / d_i of a point
-      // is formed in each pass rather than kept for all points (registers)
+      // one pass over the points per CPP columns: a point's y y^H is formed
+      // once per pass and its weights 1 / d_i in the pass (rather than kept for
+      // all points: registers)
+      constexpr int CPP = kResColsPerPass<I>;
+      if constexpr (CPP == 1) {
 #pragma unroll
-      for (int i = 0; i < I; ++i) {
-        float A[I * I];
+        for (int i = 0; i < I; ++i) {
+          float A[I * I];
 #pragma unroll
-        for (int q = 0; q < I * I; ++q) A[q] = 0.f;
+          for (int q = 0; q < I * I; ++q) A[q] = 0.f;
+#pragma unroll
+          for (int k = 0; k < NPT; ++k)
+            if (wbase + k * T < s.N) {
+              float d = 0.f;  // y = 0 and v kept past N: finite, adds nothing
+#pragma unroll
+              for (int j = 0; j < J; ++j) d = fmaf(v[k][j], lam[j][i], d);
+              herm_rank1_acc<I>(A, rcp(d), yr[k], yi[k]);
+            }
+          wave_totals_to_lds<I * I>(A, redQ + i * VQ, QSTRIDE);
+        }
+      } else {
+#pragma unroll
+      for (int i0 = 0; i0 < I; i0 += CPP) {
+        float A[CPP][I * I];
+#pragma unroll
+        for (int ci = 0; ci < CPP; ++ci)
+#pragma unroll
+          for (int q = 0; q < I * I; ++q) A[ci][q] = 0.f;
 #pragma unroll
         for (int k = 0; k < NPT; ++k)
           if (wbase + k * T < s.N) {
-            float d = 0.f;  // y = 0 and v kept past N: finite, adds nothing
+            float z[I * I];
+            herm_outer<I>(z, yr[k], yi[k]);
 #pragma unroll
-            for (int j = 0; j < J; ++j) d = fmaf(v[k][j], lam[j][i], d);
-            herm_rank1_acc<I>(A, rcp(d), yr[k], yi[k]);
+            for (int ci = 0; ci < CPP; ++ci) {
+              if (i0 + ci < I) {
+                float d = 0.f;  // y = 0 and v kept past N: finite, adds nothing
+#pragma unroll
+                for (int j = 0; j < J; ++j) d = fmaf(v[k][j], lam[j][i0 + ci], d);
+                const float w = rcp(d);
+#pragma unroll
+                for (int q = 0; q < I * I; ++q) A[ci][q] = fmaf(w, z[q], A[ci][q]);
+              }
+            }
           }
-        wave_totals_to_lds<I * I>(A, redQ + i * VQ, QSTRIDE);
+#pragma unroll
+        for (int ci = 0; ci < CPP; ++ci)
+          if (i0 + ci < I) wave_totals_to_lds<I * I>(A[ci], redQ + (i0 + ci) * VQ, QSTRIDE);
+      }
       }
     }
     __syncthreads();
@@ -417,7 +455,12 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident_batch(const DevSta
                                                                     int n_iter) {
   const int2 t = tiles[blockIdx.x];
   const DevState s = states[t.x];
-  as_resident_body<I, J, NPT, false, kGen>(s, t.y, 1, n_iter);
+  // one bin per workgroup, passed as a value the optimiser cannot see: with
+  // the constant, the I = 6 kernels came out at 512 registers plus scratch
+  // spills (389 and none with the run-time value)
+  int nb = 1;
+  asm volatile("" : "+s"(nb));
+  as_resident_body<I, J, NPT, false, kGen>(s, t.y, nb, n_iter);
 }
 
 // Register budget of the resident kernel: NPT points of y (2I), v (J), the
