@@ -37,9 +37,13 @@ template <int I>
 constexpr bool kResXInRegs = (I <= 4);
 
 // Above I = 4 the eq. 23 sums of the resident kernel take several passes
-// over the points, CPP columns each (I^2 accumulators per column).
-template <int I>
-constexpr int kResColsPerPass = (I <= 6) ? 2 : 1;
+// over the points, CPP columns each (I^2 accumulators per column, a point's
+// y y^H formed once per pass).  Where the kernel runs one wave per SIMD
+// whatever CPP (8 frames per lane at I = 6; and at I = 5 with J >= 5), it
+// takes the fewest passes that fit; elsewhere two columns per pass keep two
+// waves per SIMD.
+template <int I, int J, int NPT>
+constexpr int kResColsPerPass = (I == 5) ? ((NPT >= 8 && J >= 5) ? 5 : 2) : (I == 6) ? (NPT >= 8 ? 3 : 2) : 1;
 
 // use(k, t_k) for k < V, t_k the sum of the per-wave partials
 // part[w * stride + k] over the nw waves (nw in {1, 2, 4}, uniform), summed in
@@ -225,7 +229,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       // one pass over the points per CPP columns: a point's y y^H is formed
       // once per pass and its weights 1 / d_i in the pass (rather than kept for
       // all points: registers)
-      constexpr int CPP = kResColsPerPass<I>;
+      constexpr int CPP = kResColsPerPass<I, J, NPT>;
       if constexpr (CPP == 1) {
 #pragma unroll
         for (int i = 0; i < I; ++i) {
