@@ -78,12 +78,9 @@ hipError_t copy_tape_state(const fca_ctx* c, const TapeLayout& t, size_t dst_off
 }
 
 hipError_t copy_view(const fca_ctx* c, StateView dst, const float* v, const float* lam, const float2* P) {
-  hipError_t e = hipMemcpyAsync(dst.v, v, sizeof(float) * (size_t)c->F * c->J * c->s.Npad, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dst.lam, lam, sizeof(float) * (size_t)c->F * c->J * c->I, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dst.P, P, sizeof(float2) * (size_t)c->F * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
-  return e;
+  return fca::launch_copy3(dst.v, v, (long long)c->F * c->J * c->s.Npad, dst.lam, lam, (long long)c->F * c->J * c->I,
+                           reinterpret_cast<float*>(dst.P), reinterpret_cast<const float*>(P),
+                           2LL * c->F * c->I * c->I, c->stream);
 }
 
 DevState view_state(const fca_ctx* c, StateView v) {

@@ -26,16 +26,23 @@
 
 namespace fca {
 
-// Two waves per bin: the adjoint kernels need ~250 VGPRs at I = J = 3 (two
-// waves per SIMD), so 4-wave workgroups fit two per CU and the 513th bin of
-// a 513-bin problem waited for a second round; 2-wave workgroups fit four.
-constexpr int kAdjBlock = 128;
+// Lanes per bin.  Up to I = 3 the adjoint kernels fit in 128 VGPRs (four
+// waves per SIMD), so four waves per bin still keep all 513 bins of a
+// 513-bin problem resident at once and halve the frames per lane; above, two
+// waves per bin.
+template <int I>
+constexpr int kAdjBlock = (I <= 3) ? 256 : 128;
+
+// Whether the frame loops of the iteration adjoint request the next frame's
+// inputs ahead (more registers; above I = 5 it would cost a wave per SIMD).
+template <int I>
+constexpr bool kAdjPrefetch = (I <= 5);
 
 template <int I, int J>
 constexpr int adj_red_size() {
   constexpr int a = pad4((I * I * I <= 64) ? I * I * I : I * I);
   constexpr int b = pad4(J * I + 2 * I * I);
-  return (a > b ? a : b) * (kAdjBlock / kWave);
+  return (a > b ? a : b) * (kAdjBlock<I> / kWave);
 }
 
 // Block sum of V per-lane values into out[V] (LDS or global): transposed wave
@@ -62,42 +69,45 @@ __device__ __forceinline__ void adj_load_x(const float* xf, int Npad, int n, flo
   for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * Npad + n]; xi[i] = xf[(size_t)(I + i) * Npad + n]; }
 }
 
+// Global accesses at a byte offset from a workgroup-uniform base: the base
+// stays in scalar registers and every plane shares one 32-bit lane offset
+// (instead of a 64-bit address per plane and lane).
+__device__ __forceinline__ float ld_at(const float* base, unsigned byte_off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st_at(float* base, unsigned byte_off, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+template <int I>
+__device__ __forceinline__ void adj_load_x_at(const float* xf, int Npad, unsigned byte_off, float (&xr)[I],
+                                              float (&xi)[I]) {
+#pragma unroll
+  for (int i = 0; i < I; ++i) {
+    xr[i] = ld_at(xf + (size_t)i * Npad, byte_off);
+    xi[i] = ld_at(xf + (size_t)(I + i) * Npad, byte_off);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Adjoint of one hybrid iteration (K = 1).
 // ----------------------------------------------------------------------------
 template <int I, int J>
-__global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
+__global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a) {
   constexpr bool kOne = I * I * I <= 64;
+  constexpr int kB = kAdjBlock<I>, PH = kPH<I>;
   const int f = blockIdx.x, tid = threadIdx.x;
   const int N = s.N, Np = s.Npad;
   __shared__ float sPr[I][I], sPi[I][I];    // P_t
   __shared__ float sQr[I][I], sQi[I][I];    // Pbar of P_{t+1}
   __shared__ float sAr[I][I], sAi[I][I];    // column i: a_i
-  __shared__ float sBr[I][I], sBi[I][I];    // column i: b_i
-  __shared__ float sLt[J * I], sLn[J * I], sLb[J * I];
+  __shared__ float4 sPc[I * PH];            // P_t by columns (y = P^H x)
+  __shared__ float4 sPw[I * PH];            // P_t by rows (P ybar)
+  __shared__ float4 sAB[I * I];             // (k, i): a_ki and b_ki (re, im, re, im)
+  __shared__ float4 sLm[J * I];             // (j, i): lambda_t, lambda', lambda'bar total, 1 / lambda_t
+  __shared__ float sLb[J * I];
   __shared__ float sS[I][I * I];            // S_i, packed Hermitian
   __shared__ float sOut[J * I + 2 * I * I];
   __shared__ float red[adj_red_size<I, J>()];
-
-  for (int t = tid; t < I * I; t += kAdjBlock) {
-    const float2 p = a.P_t[(size_t)f * I * I + t], q = a.Pb_in[(size_t)f * I * I + t];
-    sPr[t / I][t % I] = p.x; sPi[t / I][t % I] = p.y;
-    sQr[t / I][t % I] = q.x; sQi[t / I][t % I] = q.y;
-  }
-  for (int t = tid; t < J * I; t += kAdjBlock) {
-    sLt[t] = a.lam_t[(size_t)f * J * I + t];
-    sLn[t] = a.lam_n[(size_t)f * J * I + t];
-  }
-  __syncthreads();
-  float Pr[I][I], Pi[I][I], lt[J][I], ln[J][I];
-#pragma unroll
-  for (int r = 0; r < I; ++r)
-#pragma unroll
-    for (int c = 0; c < I; ++c) { Pr[r][c] = sPr[r][c]; Pi[r][c] = sPi[r][c]; }
-#pragma unroll
-  for (int j = 0; j < J; ++j)
-#pragma unroll
-    for (int i = 0; i < I; ++i) { lt[j][i] = sLt[j * I + i]; ln[j][i] = sLn[j * I + i]; }
 
   const float* xf = s.xs + (size_t)f * 2 * I * Np;
   const float* vt = a.v_t + (size_t)f * J * Np;
@@ -106,15 +116,51 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
   float* vbo = a.vb_out + (size_t)f * J * Np;
   float* xb = a.xb + (size_t)f * 2 * I * Np;
 
-  // new weights w_i = 1 / sum_j v'_j lambda'_ji at frame n
-  auto weights = [&](int n, float (&vN)[J], float (&w)[I]) {
+  // Every frame loop below requests the next frame's inputs before it works
+  // on the current one (one global-memory latency per pass instead of one
+  // per frame); the first frame of pass 1 is requested here, before the
+  // per-bin set-up.
+  auto load1 = [&](int n, float (&xr)[I], float (&xi)[I], float (&vN)[J]) {
+    unsigned u = 4u * n;
+    asm volatile("" : "+v"(u));
+    adj_load_x_at<I>(xf, Np, u, xr, xi);
 #pragma unroll
-    for (int j = 0; j < J; ++j) vN[j] = vn[(size_t)j * Np + n];
+    for (int j = 0; j < J; ++j) vN[j] = ld_at(vn + (size_t)j * Np, u);
+  };
+  float pxr[I], pxi[I], pvN[J];
+  if (kAdjPrefetch<I> && tid < N) load1(tid, pxr, pxi, pvN);
+
+  // The per-bin constants are read from LDS inside the frame loops (behind an
+  // opaque zero offset, so they are not hoisted into registers): the
+  // registers go to more waves per SIMD instead.
+  const float2* Pt = a.P_t + (size_t)f * I * I;
+  for (int t = tid; t < I * I; t += kB) {
+    const float2 p = Pt[t], q = a.Pb_in[(size_t)f * I * I + t];
+    sPr[t / I][t % I] = p.x; sPi[t / I][t % I] = p.y;
+    sQr[t / I][t % I] = q.x; sQi[t / I][t % I] = q.y;
+  }
+  stage_P_columns<I>(Pt, sPc);
+  for (int t = tid; t < I * PH; t += kB) {
+    const int r = t / PH, k = 2 * (t % PH);
+    const float2 p0 = Pt[r * I + k];
+    const float2 p1 = (k + 1 < I) ? Pt[r * I + k + 1] : make_float2(0.f, 0.f);
+    sPw[t] = make_float4(p0.x, p0.y, p1.x, p1.y);
+  }
+  for (int t = tid; t < J * I; t += kB) {
+    const float lt = a.lam_t[(size_t)f * J * I + t];
+    sLm[t] = make_float4(lt, a.lam_n[(size_t)f * J * I + t], a.lb_in[(size_t)f * J * I + t], rcp(lt));
+  }
+  if (a.S_t)
+    for (int t = tid; t < I * I * I; t += kB) (&sS[0][0])[t] = a.S_t[(size_t)f * I * I * I + t];
+  __syncthreads();
+
+  // new weights w_i = 1 / sum_j v'_j lambda'_ji at a frame with v' = vN
+  auto weights = [&](const float4* lm, const float (&vN)[J], float (&w)[I]) {
 #pragma unroll
     for (int i = 0; i < I; ++i) {
       float d = 0.f;
 #pragma unroll
-      for (int j = 0; j < J; ++j) d = fmaf(vN[j], ln[j][i], d);
+      for (int j = 0; j < J; ++j) d = fmaf(vN[j], lm[j * I + i].y, d);
       w[i] = rcp(d);
     }
   };
@@ -122,17 +168,21 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
   // ---- pass 0: S_i = sum_n w_i y y^H (recorded by the forward run, or
   // summed again here) ------------------------------------------------------
   if (a.S_t) {
-    for (int t = tid; t < I * I * I; t += kAdjBlock) (&sS[0][0])[t] = a.S_t[(size_t)f * I * I * I + t];
-    __syncthreads();
+    // staged above
   } else if constexpr (kOne) {
     float acc[I * I * I];
 #pragma unroll
     for (int k = 0; k < I * I * I; ++k) acc[k] = 0.f;
-    for (int n = tid; n < N; n += kAdjBlock) {
+    for (int n = tid; n < N; n += kB) {
+      int zo = 0;
+      unsigned u = 4u * n;
+      asm volatile("" : "+s"(zo), "+v"(u));
       float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], z[I * I];
-      adj_load_x<I>(xf, Np, n, xr, xi);
-      as_transform<I>(Pr, Pi, xr, xi, yr, yi);
-      weights(n, vN, w);
+      adj_load_x_at<I>(xf, Np, u, xr, xi);
+#pragma unroll
+      for (int j = 0; j < J; ++j) vN[j] = ld_at(vn + (size_t)j * Np, u);
+      as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
+      weights(sLm + zo, vN, w);
       herm_outer<I>(z, yr, yi);
 #pragma unroll
       for (int i = 0; i < I; ++i)
@@ -146,11 +196,16 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
       float acc[I * I];
 #pragma unroll
       for (int k = 0; k < I * I; ++k) acc[k] = 0.f;
-      for (int n = tid; n < N; n += kAdjBlock) {
+      for (int n = tid; n < N; n += kB) {
+        int zo = 0;
+        unsigned u = 4u * n;
+        asm volatile("" : "+s"(zo), "+v"(u));
         float xr[I], xi[I], yr[I], yi[I], vN[J], w[I];
-        adj_load_x<I>(xf, Np, n, xr, xi);
-        as_transform<I>(Pr, Pi, xr, xi, yr, yi);
-        weights(n, vN, w);
+        adj_load_x_at<I>(xf, Np, u, xr, xi);
+#pragma unroll
+        for (int j = 0; j < J; ++j) vN[j] = ld_at(vn + (size_t)j * Np, u);
+        as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
+        weights(sLm + zo, vN, w);
         float wi = w[0];
 #pragma unroll
         for (int k = 1; k < I; ++k) wi = (k == i) ? w[k] : wi;
@@ -180,35 +235,34 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
 #pragma unroll
       for (int k = 0; k < I; ++k) {
         const float qr = sQr[k][c], qi = sQi[k][c];
-        tr = fmaf(Pr[k][r], qr, fmaf(Pi[k][r], qi, tr));
-        ti = fmaf(Pr[k][r], qi, fmaf(-Pi[k][r], qr, ti));
+        tr = fmaf(sPr[k][r], qr, fmaf(sPi[k][r], qi, tr));
+        ti = fmaf(sPr[k][r], qi, fmaf(-sPi[k][r], qr, ti));
       }
       br[r] = tr; bi[r] = ti;
     }
     herm_solve<I>(Sr, Si, ar, ai);
     herm_solve<I>(Sr, Si, br, bi);
 #pragma unroll
-    for (int r = 0; r < I; ++r) { sAr[r][c] = ar[r]; sAi[r][c] = ai[r]; sBr[r][c] = br[r]; sBi[r][c] = bi[r]; }
+    for (int r = 0; r < I; ++r) {
+      sAr[r][c] = ar[r]; sAi[r][c] = ai[r];
+      sAB[r * I + c] = make_float4(ar[r], ai[r], br[r], bi[r]);
+    }
   }
   __syncthreads();
-  float Ar[I][I], Ai[I][I], Br[I][I], Bi[I][I];
-#pragma unroll
-  for (int r = 0; r < I; ++r)
-#pragma unroll
-    for (int c = 0; c < I; ++c) { Ar[r][c] = sAr[r][c]; Ai[r][c] = sAi[r][c]; Br[r][c] = sBr[r][c]; Bi[r][c] = sBi[r][c]; }
 
   // d'bar_i at frame n, with alpha_i = a_i^H y and beta_i = b_i^H y
-  auto dprime_bar = [&](const float (&yr)[I], const float (&yi)[I], const float (&w)[I], float (&alr)[I],
-                        float (&ali)[I], float (&ber)[I], float (&bei)[I], float (&dpb)[I]) {
+  auto dprime_bar = [&](const float4* ab, const float (&yr)[I], const float (&yi)[I], const float (&w)[I],
+                        float (&alr)[I], float (&ali)[I], float (&ber)[I], float (&bei)[I], float (&dpb)[I]) {
 #pragma unroll
     for (int i = 0; i < I; ++i) {
       float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
 #pragma unroll
       for (int k = 0; k < I; ++k) {
-        a0 = fmaf(Ar[k][i], yr[k], fmaf(Ai[k][i], yi[k], a0));
-        a1 = fmaf(Ar[k][i], yi[k], fmaf(-Ai[k][i], yr[k], a1));
-        b0 = fmaf(Br[k][i], yr[k], fmaf(Bi[k][i], yi[k], b0));
-        b1 = fmaf(Br[k][i], yi[k], fmaf(-Bi[k][i], yr[k], b1));
+        const float4 q = ab[k * I + i];
+        a0 = fmaf(q.x, yr[k], fmaf(q.y, yi[k], a0));
+        a1 = fmaf(q.x, yi[k], fmaf(-q.y, yr[k], a1));
+        b0 = fmaf(q.z, yr[k], fmaf(q.w, yi[k], b0));
+        b1 = fmaf(q.z, yi[k], fmaf(-q.w, yr[k], b1));
       }
       alr[i] = a0; ali[i] = a1; ber[i] = b0; bei[i] = b1;
       const float wbar = -fmaf(b0, a0, b1 * a1);  // -Re(conj(beta) alpha)
@@ -216,56 +270,89 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
     }
   };
 
+  // the inputs of a pass-2 frame: x, v', v, v'bar-in and the xbar so far
+  auto load2 = [&](int n, float (&xr)[I], float (&xi)[I], float (&vN)[J], float (&v)[J], float (&vb)[J],
+                   float (&xbr)[I], float (&xbi)[I]) {
+    unsigned u = 4u * n;
+    asm volatile("" : "+v"(u));
+    adj_load_x_at<I>(xf, Np, u, xr, xi);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      vN[j] = ld_at(vn + (size_t)j * Np, u);
+      v[j] = ld_at(vt + (size_t)j * Np, u);
+      vb[j] = ld_at(vbi + (size_t)j * Np, u);
+    }
+    adj_load_x_at<I>(xb, Np, u, xbr, xbi);
+  };
+  float qxr[I], qxi[I], qvN[J], qv[J], qvb[J], qxbr[I], qxbi[I];
+
   // ---- pass 1: lambda'bar total = lambda'bar_in + sum_n d'bar v' ----------
   {
     float acc[J * I];
 #pragma unroll
     for (int k = 0; k < J * I; ++k) acc[k] = 0.f;
-    for (int n = tid; n < N; n += kAdjBlock) {
+    for (int n = tid; n < N; n += kB) {
       float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I];
-      adj_load_x<I>(xf, Np, n, xr, xi);
-      as_transform<I>(Pr, Pi, xr, xi, yr, yi);
-      weights(n, vN, w);
-      dprime_bar(yr, yi, w, alr, ali, ber, bei, dpb);
+      if constexpr (kAdjPrefetch<I>) {
+#pragma unroll
+        for (int i = 0; i < I; ++i) { xr[i] = pxr[i]; xi[i] = pxi[i]; }
+#pragma unroll
+        for (int j = 0; j < J; ++j) vN[j] = pvN[j];
+        if (n + kB < N) load1(n + kB, pxr, pxi, pvN);
+      } else {
+        load1(n, xr, xi, vN);
+      }
+      int zo = 0;
+      asm volatile("" : "+s"(zo));
+      as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
+      weights(sLm + zo, vN, w);
+      dprime_bar(sAB + zo, yr, yi, w, alr, ali, ber, bei, dpb);
 #pragma unroll
       for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int i = 0; i < I; ++i) acc[j * I + i] = fmaf(dpb[i], vN[j], acc[j * I + i]);
     }
+    if (kAdjPrefetch<I> && tid < N) load2(tid, qxr, qxi, qvN, qv, qvb, qxbr, qxbi);  // first frame of pass 2
     block_sum_t<J * I>(acc, sLb, red);
-    for (int t = tid; t < J * I; t += kAdjBlock) sLb[t] += a.lb_in[(size_t)f * J * I + t];
+    for (int t = tid; t < J * I; t += kB) sLm[t].z += sLb[t];
     __syncthreads();
   }
-  float lb[J][I];
-#pragma unroll
-  for (int j = 0; j < J; ++j)
-#pragma unroll
-    for (int i = 0; i < I; ++i) lb[j][i] = sLb[j * I + i];
 
   // ---- pass 2: everything else ----------------------------------------------
   const float invN = 1.0f / float(N), invI = 1.0f / float(I);
-  float il[J][I];  // 1 / lambda_t
-#pragma unroll
-  for (int j = 0; j < J; ++j)
-#pragma unroll
-    for (int i = 0; i < I; ++i) il[j][i] = rcp(lt[j][i]);
   float acc[J * I + 2 * I * I];  // lambda-bar sums, then sum_n x ybar^H (re, im)
 #pragma unroll
   for (int k = 0; k < J * I + 2 * I * I; ++k) acc[k] = 0.f;
-  for (int n = tid; n < N; n += kAdjBlock) {
+  for (int n = tid; n < N; n += kB) {
     float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I], v[J], vb[J];
-    adj_load_x<I>(xf, Np, n, xr, xi);
-    as_transform<I>(Pr, Pi, xr, xi, yr, yi);
-    weights(n, vN, w);
-    dprime_bar(yr, yi, w, alr, ali, ber, bei, dpb);
+    float xbr[I], xbi[I];
+    if constexpr (kAdjPrefetch<I>) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) { v[j] = vt[(size_t)j * Np + n]; vb[j] = vbi[(size_t)j * Np + n]; }
+      for (int i = 0; i < I; ++i) { xr[i] = qxr[i]; xi[i] = qxi[i]; xbr[i] = qxbr[i]; xbi[i] = qxbi[i]; }
+#pragma unroll
+      for (int j = 0; j < J; ++j) { vN[j] = qvN[j]; v[j] = qv[j]; vb[j] = qvb[j]; }
+      if (n + kB < N) load2(n + kB, qxr, qxi, qvN, qv, qvb, qxbr, qxbi);
+    } else {
+      load1(n, xr, xi, vN);
+      unsigned u = 4u * n;
+      asm volatile("" : "+v"(u));
+#pragma unroll
+      for (int j = 0; j < J; ++j) { v[j] = ld_at(vt + (size_t)j * Np, u); vb[j] = ld_at(vbi + (size_t)j * Np, u); }
+    }
+    int zo = 0;
+    unsigned u = 4u * n;
+    asm volatile("" : "+s"(zo), "+v"(u));
+    as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
+    weights(sLm + zo, vN, w);
+    dprime_bar(sAB + zo, yr, yi, w, alr, ali, ber, bei, dpb);
     float id[I], e[I];  // 1 / d_i, |y_i|^2
+    asm volatile("" : "+s"(zo));
+    const float4* lm = sLm + zo;
 #pragma unroll
     for (int i = 0; i < I; ++i) {
       float t = 0.f;
 #pragma unroll
-      for (int j = 0; j < J; ++j) t = fmaf(v[j], lt[j][i], t);
+      for (int j = 0; j < J; ++j) t = fmaf(v[j], lm[j * I + i].x, t);
       id[i] = rcp(t);
       e[i] = fmaf(yr[i], yr[i], yi[i] * yi[i]);
     }
@@ -275,44 +362,52 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
     for (int i = 0; i < I; ++i) { db2[i] = 0.f; eb[i] = 0.f; }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
+      asm volatile("" : "+s"(zo));
+      lm = sLm + zo;
       const float ivn = rcp(vN[j]);
       float vbt = vb[j], rl = 0.f;
       float r[I], g[I];
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        vbt = fmaf(dpb[i], ln[j][i], vbt);
-        const float q = v[j] * lt[j][i];
+        const float4 L = lm[j * I + i];
+        vbt = fmaf(dpb[i], L.y, vbt);
+        const float q = v[j] * L.x;
         g[i] = q * id[i];
         r[i] = fmaf(g[i] * g[i], e[i], q * (1.f - g[i]));
-        rl = fmaf(lb[j][i], r[i], rl);
+        rl = fmaf(L.z, r[i], rl);
       }
       vbt -= rl * invN * ivn * ivn;
       float vj = 0.f;
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        const float rbar = fmaf(lb[j][i], invN * ivn, vbt * invI * il[j][i]);
-        acc[j * I + i] = fmaf(-vbt * r[i] * invI, il[j][i] * il[j][i], acc[j * I + i]);
+        const float4 L = lm[j * I + i];
+        const float rbar = fmaf(L.z, invN * ivn, vbt * invI * L.w);
+        acc[j * I + i] = fmaf(-vbt * r[i] * invI, L.w * L.w, acc[j * I + i]);
         const float gi = g[i];
         const float dq = fmaf(2.f * gi * id[i], e[i], 1.f - 2.f * gi);   // dr/dq
         const float dd = gi * gi * fmaf(-2.f * e[i], id[i], 1.f);        // dr/dd
         const float qbar = rbar * dq;
         db2[i] = fmaf(rbar, dd, db2[i]);
         eb[i] = fmaf(rbar, gi * gi, eb[i]);                         // dr/d|y|^2 = g^2
-        vj = fmaf(qbar, lt[j][i], vj);
+        vj = fmaf(qbar, L.x, vj);
         acc[j * I + i] = fmaf(qbar, v[j], acc[j * I + i]);
       }
       vbar[j] = vj;
     }
+    asm volatile("" : "+s"(zo));
+    lm = sLm + zo;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        vbar[j] = fmaf(db2[i], lt[j][i], vbar[j]);
+        vbar[j] = fmaf(db2[i], lm[j * I + i].x, vbar[j]);
         acc[j * I + i] = fmaf(db2[i], v[j], acc[j * I + i]);
       }
-      vbo[(size_t)j * Np + n] = vbar[j];
+      st_at(vbo + (size_t)j * Np, u, vbar[j]);
     }
     // ybar = -sum_i w_i (b_i alpha_i + a_i beta_i) + 2 eb y
+    asm volatile("" : "+s"(zo));
+    const float4* ab = sAB + zo;
     float ybr[I], ybi[I];
 #pragma unroll
     for (int k = 0; k < I; ++k) {
@@ -320,24 +415,37 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
 #pragma unroll
       for (int i = 0; i < I; ++i) {
         // b_ki alpha_i + a_ki beta_i
-        const float ur = (Br[k][i] * alr[i] - Bi[k][i] * ali[i]) + (Ar[k][i] * ber[i] - Ai[k][i] * bei[i]);
-        const float ui = (Br[k][i] * ali[i] + Bi[k][i] * alr[i]) + (Ar[k][i] * bei[i] + Ai[k][i] * ber[i]);
+        const float4 q = ab[k * I + i];
+        const float ur = (q.z * alr[i] - q.w * ali[i]) + (q.x * ber[i] - q.y * bei[i]);
+        const float ui = (q.z * ali[i] + q.w * alr[i]) + (q.x * bei[i] + q.y * ber[i]);
         tr = fmaf(-w[i], ur, tr);
         ti = fmaf(-w[i], ui, ti);
       }
       ybr[k] = tr; ybi[k] = ti;
     }
     // xbar += P ybar;  sum_n x ybar^H
+    asm volatile("" : "+s"(zo));
+    const float4* pw = sPw + zo;
 #pragma unroll
     for (int r = 0; r < I; ++r) {
       float tr = 0.f, ti = 0.f;
 #pragma unroll
-      for (int k = 0; k < I; ++k) {
-        tr = fmaf(Pr[r][k], ybr[k], fmaf(-Pi[r][k], ybi[k], tr));
-        ti = fmaf(Pr[r][k], ybi[k], fmaf(Pi[r][k], ybr[k], ti));
+      for (int h = 0; h < PH; ++h) {
+        const float4 q = pw[r * PH + h];
+        const int k = 2 * h;
+        tr = fmaf(q.x, ybr[k], fmaf(-q.y, ybi[k], tr));
+        ti = fmaf(q.x, ybi[k], fmaf(q.y, ybr[k], ti));
+        if (k + 1 < I) {
+          tr = fmaf(q.z, ybr[k + 1], fmaf(-q.w, ybi[k + 1], tr));
+          ti = fmaf(q.z, ybi[k + 1], fmaf(q.w, ybr[k + 1], ti));
+        }
       }
-      xb[(size_t)r * Np + n] += tr;
-      xb[(size_t)(I + r) * Np + n] += ti;
+      if constexpr (!kAdjPrefetch<I>) {  // xbar so far, read late to keep it out of the frame's registers
+        xbr[r] = ld_at(xb + (size_t)r * Np, u);
+        xbi[r] = ld_at(xb + (size_t)(I + r) * Np, u);
+      }
+      st_at(xb + (size_t)r * Np, u, xbr[r] + tr);
+      st_at(xb + (size_t)(I + r) * Np, u, xbi[r] + ti);
 #pragma unroll
       for (int k = 0; k < I; ++k) {
         // x_r conj(ybar_k)
@@ -347,8 +455,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
     }
   }
   block_sum_t<J * I + 2 * I * I>(acc, sOut, red);
-  for (int t = tid; t < J * I; t += kAdjBlock) a.lb_out[(size_t)f * J * I + t] = sOut[t];
-  for (int t = tid; t < I * I; t += kAdjBlock) {
+  for (int t = tid; t < J * I; t += kB) a.lb_out[(size_t)f * J * I + t] = sOut[t];
+  for (int t = tid; t < I * I; t += kB) {
     const int r = t / I, c = t % I;
     // (Pbar_new A^H)_rc = sum_k Pbar_rk conj(A_ck)
     float tr = sOut[J * I + t], ti = sOut[J * I + I * I + t];
@@ -367,29 +475,33 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_iter(DevState s, AdjIter a) {
 // and initialises xb.
 // ----------------------------------------------------------------------------
 template <int I, int J>
-__global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const float2* __restrict__ gout, AdjIter a) {
+__global__ __launch_bounds__(kAdjBlock<I>) void k_adj_wiener(DevState s, const float2* __restrict__ gout, AdjIter a) {
+  constexpr int kB = kAdjBlock<I>, PH = kPH<I>;
   const int f = blockIdx.x, tid = threadIdx.x;
   const int N = s.N, Np = s.Npad, F = s.F;
-  __shared__ float sPr[I][I], sPi[I][I], sBr[I][I], sBi[I][I];
+  __shared__ float sBr[I][I], sBi[I][I];
+  __shared__ float4 sPc[I * PH];  // P by columns (y = P^H x)
+  __shared__ float4 sPw[I * PH];  // P by rows (P ybar)
+  __shared__ float4 sBc[I * PH];  // B by columns (zbar = B^H sbar)
   __shared__ float sL[J * I];
   __shared__ float sOut[J * I + 4 * I * I];
-  __shared__ float red[pad4(J * I + 4 * I * I) * (kAdjBlock / kWave)];
-  for (int t = tid; t < I * I; t += kAdjBlock) {
-    const float2 p = s.P[(size_t)f * I * I + t], b = s.Bm[(size_t)f * I * I + t];
-    sPr[t / I][t % I] = p.x; sPi[t / I][t % I] = p.y;
+  __shared__ float red[pad4(J * I + 4 * I * I) * (kB / kWave)];
+  const float2* Pf = s.P + (size_t)f * I * I;
+  const float2* Bf = s.Bm + (size_t)f * I * I;
+  for (int t = tid; t < I * I; t += kB) {
+    const float2 b = Bf[t];
     sBr[t / I][t % I] = b.x; sBi[t / I][t % I] = b.y;
   }
-  for (int t = tid; t < J * I; t += kAdjBlock) sL[t] = s.lam[(size_t)f * J * I + t];
+  stage_P_columns<I>(Pf, sPc);
+  stage_P_columns<I>(Bf, sBc);
+  for (int t = tid; t < I * PH; t += kB) {
+    const int r = t / PH, k = 2 * (t % PH);
+    const float2 p0 = Pf[r * I + k];
+    const float2 p1 = (k + 1 < I) ? Pf[r * I + k + 1] : make_float2(0.f, 0.f);
+    sPw[t] = make_float4(p0.x, p0.y, p1.x, p1.y);
+  }
+  for (int t = tid; t < J * I; t += kB) sL[t] = s.lam[(size_t)f * J * I + t];
   __syncthreads();
-  float Pr[I][I], Pi[I][I], Br[I][I], Bi[I][I], lam[J][I];
-#pragma unroll
-  for (int r = 0; r < I; ++r)
-#pragma unroll
-    for (int c = 0; c < I; ++c) { Pr[r][c] = sPr[r][c]; Pi[r][c] = sPi[r][c]; Br[r][c] = sBr[r][c]; Bi[r][c] = sBi[r][c]; }
-#pragma unroll
-  for (int j = 0; j < J; ++j)
-#pragma unroll
-    for (int i = 0; i < I; ++i) lam[j][i] = sL[j * I + i];
   const float* xf = s.xs + (size_t)f * 2 * I * Np;
   const float* vf = s.vs + (size_t)f * J * Np;
   float* vbo = a.vb_out + (size_t)f * J * Np;
@@ -398,17 +510,25 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const floa
   float acc[J * I + 4 * I * I];
 #pragma unroll
   for (int k = 0; k < J * I + 4 * I * I; ++k) acc[k] = 0.f;
-  for (int n = tid; n < N; n += kAdjBlock) {
+  for (int n = tid; n < N; n += kB) {
+    // per-bin constants come from LDS behind opaque zero offsets (fresh per
+    // use, so no read is kept live across the frame); one 32-bit lane offset
+    // serves every plane
+    int zo = 0;
+    unsigned u = 4u * n;
+    asm volatile("" : "+s"(zo), "+v"(u));
     float xr[I], xi[I], yr[I], yi[I], v[J], d[I];
-    adj_load_x<I>(xf, Np, n, xr, xi);
-    as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+    adj_load_x_at<I>(xf, Np, u, xr, xi);
+    as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
 #pragma unroll
-    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * Np + n];
+    for (int j = 0; j < J; ++j) v[j] = ld_at(vf + (size_t)j * Np, u);
+    asm volatile("" : "+s"(zo));
+    const float* lam = sL + zo;
 #pragma unroll
     for (int i = 0; i < I; ++i) {
       float t = 0.f;
 #pragma unroll
-      for (int j = 0; j < J; ++j) t = fmaf(v[j], lam[j][i], t);
+      for (int j = 0; j < J; ++j) t = fmaf(v[j], lam[j * I + i], t);
       d[i] = t;
     }
     float ybr[I], ybi[I], dbar[I], id[I];
@@ -418,18 +538,28 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const floa
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float sr[I], si[I];
-      const float2* gp = gout + (((size_t)j * F + f) * N + n) * I;
+      // s_j at frame n: I interleaved complex values at byte offset 2 I u
+      const float* gp = reinterpret_cast<const float*>(gout + ((size_t)j * F + f) * N * I);
 #pragma unroll
-      for (int i = 0; i < I; ++i) { const float2 t = gp[i]; sr[i] = t.x; si[i] = t.y; }
+      for (int i = 0; i < I; ++i) { sr[i] = ld_at(gp + 2 * i, u * (2 * I)); si[i] = ld_at(gp + 2 * i + 1, u * (2 * I)); }
+      asm volatile("" : "+s"(zo));
+      const float4* bc = sBc + zo;
+      lam = sL + zo;
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        const float q = v[j] * lam[j][i], g = q * id[i];
+        const float q = v[j] * lam[j * I + i], g = q * id[i];
         // zbar_i = (B^H sbar)_i = sum_k conj(B_ki) sbar_k
         float zr = 0.f, zi = 0.f;
 #pragma unroll
-        for (int k = 0; k < I; ++k) {
-          zr = fmaf(Br[k][i], sr[k], fmaf(Bi[k][i], si[k], zr));
-          zi = fmaf(Br[k][i], si[k], fmaf(-Bi[k][i], sr[k], zi));
+        for (int h = 0; h < PH; ++h) {
+          const float4 b = bc[i * PH + h];
+          const int k = 2 * h;
+          zr = fmaf(b.x, sr[k], fmaf(b.y, si[k], zr));
+          zi = fmaf(b.x, si[k], fmaf(-b.y, sr[k], zi));
+          if (k + 1 < I) {
+            zr = fmaf(b.z, sr[k + 1], fmaf(b.w, si[k + 1], zr));
+            zi = fmaf(b.z, si[k + 1], fmaf(-b.w, sr[k + 1], zi));
+          }
         }
         const float gbar = fmaf(yr[i], zr, yi[i] * zi);   // Re(conj(y) zbar)
         ybr[i] = fmaf(g, zr, ybr[i]);
@@ -445,27 +575,37 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const floa
         }
       }
     }
+    asm volatile("" : "+s"(zo));
+    lam = sL + zo;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float vb = 0.f;
 #pragma unroll
       for (int i = 0; i < I; ++i) {
         const float t = qb[j][i] + dbar[i];
-        vb = fmaf(t, lam[j][i], vb);
+        vb = fmaf(t, lam[j * I + i], vb);
         acc[j * I + i] = fmaf(t, v[j], acc[j * I + i]);
       }
-      vbo[(size_t)j * Np + n] = vb;
+      st_at(vbo + (size_t)j * Np, u, vb);
     }
+    asm volatile("" : "+s"(zo));
+    const float4* pw = sPw + zo;
 #pragma unroll
     for (int r = 0; r < I; ++r) {
       float tr = 0.f, ti = 0.f;
 #pragma unroll
-      for (int k = 0; k < I; ++k) {
-        tr = fmaf(Pr[r][k], ybr[k], fmaf(-Pi[r][k], ybi[k], tr));
-        ti = fmaf(Pr[r][k], ybi[k], fmaf(Pi[r][k], ybr[k], ti));
+      for (int h = 0; h < PH; ++h) {
+        const float4 q = pw[r * PH + h];
+        const int k = 2 * h;
+        tr = fmaf(q.x, ybr[k], fmaf(-q.y, ybi[k], tr));
+        ti = fmaf(q.x, ybi[k], fmaf(q.y, ybr[k], ti));
+        if (k + 1 < I) {
+          tr = fmaf(q.z, ybr[k + 1], fmaf(-q.w, ybi[k + 1], tr));
+          ti = fmaf(q.z, ybi[k + 1], fmaf(q.w, ybr[k + 1], ti));
+        }
       }
-      xb[(size_t)r * Np + n] = tr;
-      xb[(size_t)(I + r) * Np + n] = ti;
+      st_at(xb + (size_t)r * Np, u, tr);
+      st_at(xb + (size_t)(I + r) * Np, u, ti);
 #pragma unroll
       for (int k = 0; k < I; ++k) {
         acc[J * I + 2 * I * I + r * I + k] = fmaf(xr[r], ybr[k], fmaf(xi[r], ybi[k], acc[J * I + 2 * I * I + r * I + k]));
@@ -474,8 +614,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const floa
     }
   }
   block_sum_t<J * I + 4 * I * I>(acc, sOut, red);
-  for (int t = tid; t < J * I; t += kAdjBlock) a.lb_out[(size_t)f * J * I + t] = sOut[t];
-  for (int t = tid; t < I * I; t += kAdjBlock) {
+  for (int t = tid; t < J * I; t += kB) a.lb_out[(size_t)f * J * I + t] = sOut[t];
+  for (int t = tid; t < I * I; t += kB) {
     const int r = t / I, c = t % I;
     // -(B Bbar^H B)_rc + (sum_n x ybar^H)_rc
     float tr = sOut[J * I + 2 * I * I + t], ti = sOut[J * I + 3 * I * I + t];
@@ -498,14 +638,14 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_wiener(DevState s, const floa
 
 template <int I, int J>
 hipError_t launch_adj_iter(const DevState& s, const AdjIter& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_adj_iter<I, J>), dim3(s.F), dim3(kAdjBlock), 0, st, s, a);
+  hipLaunchKernelGGL((k_adj_iter<I, J>), dim3(s.F), dim3(kAdjBlock<I>), 0, st, s, a);
   return hipGetLastError();
 }
 
 template <int I, int J>
 hipError_t launch_adj_wiener(const DevState& s, const float2* gout, const AdjIter& a, hipStream_t st) {
   hipLaunchKernelGGL((k_p_inv_herm<I>), dim3((s.F * I + 63) / 64), dim3(64), 0, st, s);
-  hipLaunchKernelGGL((k_adj_wiener<I, J>), dim3(s.F), dim3(kAdjBlock), 0, st, s, gout, a);
+  hipLaunchKernelGGL((k_adj_wiener<I, J>), dim3(s.F), dim3(kAdjBlock<I>), 0, st, s, gout, a);
   return hipGetLastError();
 }
 

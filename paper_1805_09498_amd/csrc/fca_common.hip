@@ -41,6 +41,30 @@ __global__ void k_unpack_x(const float* __restrict__ xs, float2* __restrict__ x,
   for (int i = 0; i < I; ++i) x[((size_t)f * N + n) * I + i] = make_float2(src[(size_t)i * Npad], src[(size_t)(I + i) * Npad]);
 }
 
+// Up to three device-to-device copies of float arrays in one launch
+// (blockIdx.y picks the array; 16-byte moves where both ends allow them).
+struct Copy3 {
+  float* dst[3];
+  const float* src[3];
+  long long n[3];
+};
+
+__global__ void k_copy3(Copy3 c) {
+  const int a = blockIdx.y;
+  float* d = c.dst[a];
+  const float* s = c.src[a];
+  const long long n = c.n[a];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (((reinterpret_cast<unsigned long long>(d) | reinterpret_cast<unsigned long long>(s)) & 15) == 0) {
+    const long long n4 = n / 4;
+    for (long long i = t0; i < n4; i += stride) reinterpret_cast<float4*>(d)[i] = reinterpret_cast<const float4*>(s)[i];
+    for (long long i = n4 * 4 + t0; i < n; i += stride) d[i] = s[i];
+  } else {
+    for (long long i = t0; i < n; i += stride) d[i] = s[i];
+  }
+}
+
 __global__ void k_check_finite(const float* __restrict__ a, long long n, int* flag) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -69,6 +93,18 @@ hipError_t launch_pack_x(const float2* x, float* xs, int F, int N, int I, int Np
   hipLaunchKernelGGL(k_pack_x, dim3(blocks_for((long long)F * Npad, 256)), dim3(256), 0, st, x, xs, F, N, I, Npad);
   return hipGetLastError();
 }
+hipError_t launch_copy3(float* d0, const float* s0, long long n0, float* d1, const float* s1, long long n1, float* d2,
+                        const float* s2, long long n2, hipStream_t st) {
+  Copy3 c{{d0, d1, d2}, {s0, s1, s2}, {n0 > 0 ? n0 : 0, n1 > 0 ? n1 : 0, n2 > 0 ? n2 : 0}};
+  long long mx = c.n[0] > c.n[1] ? c.n[0] : c.n[1];
+  mx = mx > c.n[2] ? mx : c.n[2];
+  if (mx == 0) return hipSuccess;
+  long long bx = (mx / 4 + 255) / 256;
+  bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+  hipLaunchKernelGGL(k_copy3, dim3((unsigned)bx, 3), dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_v(const float* v, float* vs, int F, int N, int J, int Npad, hipStream_t st) {
   hipLaunchKernelGGL(k_pack_v, dim3(blocks_for((long long)F * Npad, 256)), dim3(256), 0, st, v, vs, F, N, J, Npad);
   return hipGetLastError();

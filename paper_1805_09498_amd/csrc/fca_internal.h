@@ -33,6 +33,11 @@ struct fca_ctx {
 };
 
 namespace fca {
+// Three float-array device copies (n floats each; n = 0 skips one) in one
+// launch (fca_common.hip).
+hipError_t launch_copy3(float* d0, const float* s0, long long n0, float* d1, const float* s1, long long n1, float* d2,
+                        const float* s2, long long n2, hipStream_t st);
+
 // Save the iterated state of a context to its backup region, or restore it.
 hipError_t copy_state(fca_ctx* c, bool save);
 
