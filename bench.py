@@ -256,7 +256,7 @@ def main():
         batch_main(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the frequency bins shard across "
+        print(json.dumps({"error": "bench.py measures one GPU only; the frequency bins shard across "
                                    "GPUs without communication, but no multi-GPU run is implemented"}))
         sys.exit(2)
     import torch
