@@ -103,6 +103,7 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
   __shared__ float4 sPc[I * PH];            // P_t by columns (y = P^H x)
   __shared__ float4 sPw[I * PH];            // P_t by rows (P ybar)
   __shared__ float4 sAB[I * I];             // (k, i): a_ki and b_ki (re, im, re, im)
+  __shared__ float4 sPA[I * PH], sPB[I * PH];  // P A and P B by columns (alpha = (P a)^H x)
   __shared__ float4 sLm[J * I];             // (j, i): lambda_t, lambda', lambda'bar total, 1 / lambda_t
   __shared__ float sLb[J * I];
   __shared__ float sS[I][I * I];            // S_i, packed Hermitian
@@ -247,6 +248,28 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
       sAr[r][c] = ar[r]; sAi[r][c] = ai[r];
       sAB[r * I + c] = make_float4(ar[r], ai[r], br[r], bi[r]);
     }
+    // column c of P A and of P B, in the column staging of P
+    float par[I], pai[I], pbr[I], pbi[I];
+#pragma unroll
+    for (int r = 0; r < I; ++r) {
+      float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        const float pr = sPr[r][k], pi = sPi[r][k];
+        t0 = fmaf(pr, ar[k], fmaf(-pi, ai[k], t0));
+        t1 = fmaf(pr, ai[k], fmaf(pi, ar[k], t1));
+        t2 = fmaf(pr, br[k], fmaf(-pi, bi[k], t2));
+        t3 = fmaf(pr, bi[k], fmaf(pi, br[k], t3));
+      }
+      par[r] = t0; pai[r] = t1; pbr[r] = t2; pbi[r] = t3;
+    }
+#pragma unroll
+    for (int hh = 0; hh < PH; ++hh) {
+      const int k = 2 * hh, k1 = (k + 1) % I;  // the second entry is zero past I
+      const bool two = k + 1 < I;
+      sPA[c * PH + hh] = make_float4(par[k], pai[k], two ? par[k1] : 0.f, two ? pai[k1] : 0.f);
+      sPB[c * PH + hh] = make_float4(pbr[k], pbi[k], two ? pbr[k1] : 0.f, two ? pbi[k1] : 0.f);
+    }
   }
   __syncthreads();
 
@@ -292,7 +315,7 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
 #pragma unroll
     for (int k = 0; k < J * I; ++k) acc[k] = 0.f;
     for (int n = tid; n < N; n += kB) {
-      float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I];
+      float xr[I], xi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I];
       if constexpr (kAdjPrefetch<I>) {
 #pragma unroll
         for (int i = 0; i < I; ++i) { xr[i] = pxr[i]; xi[i] = pxi[i]; }
@@ -304,9 +327,15 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
       }
       int zo = 0;
       asm volatile("" : "+s"(zo));
-      as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
+      // alpha_i = a_i^H y = (P a_i)^H x and beta_i = (P b_i)^H x: y itself is not needed here
+      as_transform_lds<I>(sPA + zo, xr, xi, alr, ali);
+      as_transform_lds<I>(sPB + zo, xr, xi, ber, bei);
       weights(sLm + zo, vN, w);
-      dprime_bar(sAB + zo, yr, yi, w, alr, ali, ber, bei, dpb);
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const float wbar = -fmaf(ber[i], alr[i], bei[i] * ali[i]);  // -Re(conj(beta) alpha)
+        dpb[i] = -wbar * w[i] * w[i];
+      }
 #pragma unroll
       for (int j = 0; j < J; ++j)
 #pragma unroll
@@ -345,7 +374,9 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
     as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
     weights(sLm + zo, vN, w);
     dprime_bar(sAB + zo, yr, yi, w, alr, ali, ber, bei, dpb);
-    float id[I], e[I];  // 1 / d_i, |y_i|^2
+    // with h_i = |y_i|^2 / d_i - 1 and q = v lambda, g = q / d:
+    //   r = q (1 + g h),  dr/dq = 1 + 2 g h,  dr/dd = -g^2 (1 + 2 h),  dr/d|y|^2 = g^2
+    float id[I], h[I], m2[I];  // 1 / d_i, h_i, -(1 + 2 h_i)
     asm volatile("" : "+s"(zo));
     const float4* lm = sLm + zo;
 #pragma unroll
@@ -354,7 +385,8 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
 #pragma unroll
       for (int j = 0; j < J; ++j) t = fmaf(v[j], lm[j * I + i].x, t);
       id[i] = rcp(t);
-      e[i] = fmaf(yr[i], yr[i], yi[i] * yi[i]);
+      h[i] = fmaf(fmaf(yr[i], yr[i], yi[i] * yi[i]), id[i], -1.f);
+      m2[i] = fmaf(-2.f, h[i], -1.f);
     }
     // v'bar total and the rbar of every (j, i)
     float db2[I], eb[I], vbar[J];
@@ -373,22 +405,22 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
         vbt = fmaf(dpb[i], L.y, vbt);
         const float q = v[j] * L.x;
         g[i] = q * id[i];
-        r[i] = fmaf(g[i] * g[i], e[i], q * (1.f - g[i]));
+        r[i] = fmaf(q, g[i] * h[i], q);
         rl = fmaf(L.z, r[i], rl);
       }
-      vbt -= rl * invN * ivn * ivn;
+      const float an = invN * ivn;
+      vbt = fmaf(-rl * an, ivn, vbt);
+      const float bv = vbt * invI;
       float vj = 0.f;
 #pragma unroll
       for (int i = 0; i < I; ++i) {
         const float4 L = lm[j * I + i];
-        const float rbar = fmaf(L.z, invN * ivn, vbt * invI * L.w);
-        acc[j * I + i] = fmaf(-vbt * r[i] * invI, L.w * L.w, acc[j * I + i]);
-        const float gi = g[i];
-        const float dq = fmaf(2.f * gi * id[i], e[i], 1.f - 2.f * gi);   // dr/dq
-        const float dd = gi * gi * fmaf(-2.f * e[i], id[i], 1.f);        // dr/dd
-        const float qbar = rbar * dq;
-        db2[i] = fmaf(rbar, dd, db2[i]);
-        eb[i] = fmaf(rbar, gi * gi, eb[i]);                         // dr/d|y|^2 = g^2
+        const float rbar = fmaf(L.z, an, bv * L.w);
+        acc[j * I + i] = fmaf(-bv * r[i], L.w * L.w, acc[j * I + i]);
+        const float gi = g[i], g2 = gi * gi;
+        const float qbar = rbar * fmaf(2.f * gi, h[i], 1.f);  // rbar dr/dq
+        db2[i] = fmaf(rbar * g2, m2[i], db2[i]);             // rbar dr/dd
+        eb[i] = fmaf(rbar, g2, eb[i]);                        // rbar dr/d|y|^2
         vj = fmaf(qbar, L.x, vj);
         acc[j * I + i] = fmaf(qbar, v[j], acc[j * I + i]);
       }
