@@ -121,12 +121,25 @@ fca_status fastfca_as_forward(fca_ctx* c, int n_iter, int ckpt_every, fca_c64* o
   }
   c->tape_version = ~0ULL;
   int waves = 0, bpw = 0;
+  bool last_rec = false;
   for (int k = 0; k < t.n_ck; ++k) {
     if ((e = copy_view(c, state_at(c, t, t.ck_off + (size_t)k * t.state_floats), c->s.vs, c->s.lam, c->s.P)) != hipSuccess)
       return fca::ctx_hip_fail(c, e, "checkpoint copy");
     const int steps = (n_iter - k * every) < every ? (n_iter - k * every) : every;
     int w = 0, b = 0;
-    fca_status st = fca::as_iterate_chosen(c, steps, &w, &b);
+    fca_status st;
+    if (k == t.n_ck - 1) {
+      // The last segment is the first one the backward pass needs: where the
+      // shape is frequency-resident its states go straight into the tape.
+      const StateView first = state_at(c, t, t.slot_off + t.state_floats);
+      fca::Trace tr{first.v, first.lam, first.P, static_cast<float*>(c->tape) + t.S_off, (long long)t.state_floats,
+                    (long long)t.S_floats};
+      bool rec = false;
+      st = fca::as_iterate_chosen_trace(c, steps, tr, &w, &b, &rec);
+      last_rec = rec;
+    } else {
+      st = fca::as_iterate_chosen(c, steps, &w, &b);
+    }
     if (st != FCA_OK) return st;
     if (k > 0 && (w != waves || b != bpw))
       return fca::ctx_fail(c, FCA_ERR_STATE, "the launch shape changed inside a recorded run");
@@ -140,6 +153,7 @@ fca_status fastfca_as_forward(fca_ctx* c, int n_iter, int ckpt_every, fca_c64* o
   c->tape_every = every;
   c->tape_waves = waves;
   c->tape_bpw = bpw;
+  c->tape_last_rec = last_rec ? 1 : 0;
   c->tape_version = c->version;
   return FCA_OK;
 }
@@ -176,7 +190,9 @@ fca_status fastfca_as_backward(fca_ctx* c, const fca_c64* grad_out, fca_c64* gra
     const int len = (T - t0) < every ? (T - t0) : every;
     const size_t ck_at = t.ck_off + (size_t)k * t.state_floats;
     auto slot_at = [&](int j) { return j == 0 ? ck_at : t.slot_off + (size_t)j * t.state_floats; };
-    if (recorded) {
+    if (recorded && k == t.n_ck - 1 && c->tape_last_rec) {
+      // states recorded by the forward run
+    } else if (recorded) {
       if ((e = copy_tape_state(c, t, t.slot_off, ck_at)) != hipSuccess) return fca::ctx_hip_fail(c, e, "segment restore");
       const StateView first = state_at(c, t, slot_at(1));
       fca::Trace tr{first.v, first.lam, first.P, tape + t.S_off, (long long)t.state_floats, (long long)t.S_floats};

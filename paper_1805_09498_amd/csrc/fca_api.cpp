@@ -283,6 +283,20 @@ fca_status as_iterate_chosen(fca_ctx* c, int n_iter, int* waves, int* bpw) {
   return FCA_OK;
 }
 
+fca_status as_iterate_chosen_trace(fca_ctx* c, int n_iter, const Trace& tr, int* waves, int* bpw, bool* recorded) {
+  Shape sh;
+  fca_status st = choose_shape(c, n_iter, &sh);
+  if (st != FCA_OK) return st;
+  c->last_waves = sh.waves; c->last_bpw = sh.bpw;
+  *waves = sh.waves; *bpw = sh.bpw;
+  ++c->version;
+  *recorded = sh.waves > 0 && n_iter <= 1024;
+  hipError_t e = *recorded ? c->ks->as_iter_resident_trace(c->s, c->stream, n_iter, sh.waves, sh.bpw, tr)
+                           : launch_shape(c, sh, n_iter);
+  if (e != hipSuccess) return hip_fail(c, e, "FastFCA-AS iteration");
+  return FCA_OK;
+}
+
 hipError_t as_iterate_view(fca_ctx* c, const DevState& s, int waves, int bpw, int n_iter) {
   if (waves == 0) {
     for (int it = 0; it < n_iter; ++it) {
@@ -343,7 +357,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
   c->backup = nullptr; c->arena = nullptr; c->last_waves = -1; c->last_bpw = -1;
   c->version = 0; c->tape = nullptr; c->tape_bytes = 0; c->tape_iters = 0; c->tape_every = 0;
-  c->tape_waves = 0; c->tape_bpw = 0; c->tape_version = ~0ULL;
+  c->tape_waves = 0; c->tape_bpw = 0; c->tape_last_rec = 0; c->tape_version = ~0ULL;
 
   DevState& s = c->s;
   s.F = F; s.N = N; s.Npad = (int)Npad; s.K = 1;

@@ -28,6 +28,7 @@ struct fca_ctx {
   size_t tape_bytes;
   int tape_iters, tape_every;
   int tape_waves, tape_bpw;           // launch shape of the recorded iterations
+  int tape_last_rec;                  // 1: the last segment's states are already in the tape
   unsigned long long tape_version;    // version right after the recording
   std::string err;
 };
@@ -48,6 +49,9 @@ fca_status ctx_hip_fail(fca_ctx* c, hipError_t e, const char* where);
 // FastFCA-AS iterations of a context with its launch-shape choice (options,
 // tuner); the shape used is returned in *waves, *bpw (waves 0: streaming).
 fca_status as_iterate_chosen(fca_ctx* c, int n_iter, int* waves, int* bpw);
+// The same, and where the chosen shape is frequency-resident the iterations
+// run through the recording kernel into tr (*recorded = true).
+fca_status as_iterate_chosen_trace(fca_ctx* c, int n_iter, const Trace& tr, int* waves, int* bpw, bool* recorded);
 // n_iter FastFCA-AS iterations of the state view s (the context's x and
 // scratch, any v / lambda / P) with a given launch shape.
 hipError_t as_iterate_view(fca_ctx* c, const DevState& s, int waves, int bpw, int n_iter);
