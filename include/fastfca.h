@@ -110,6 +110,13 @@ fca_status fca_wiener_separate(fca_ctx *ctx, fca_c64 *out);
  * Synchronises the context's stream. */
 fca_status fca_loglik(fca_ctx *ctx, double *out);
 
+/* The same log-likelihood (eq. 5 / eq. 14), written to a DEVICE double:
+ * out_dev (8-byte aligned device pointer, owned by the caller) holds L once
+ * the context's stream has passed this call.  Asynchronous: nothing waits,
+ * so a caller can queue job after job and read the values later.
+ * FCA_ERR_ARG for a NULL or misaligned out_dev. */
+fca_status fca_loglik_device(fca_ctx *ctx, double *out_dev);
+
 /* Copy the current parameters to caller-owned device arrays in the ABI
  * layouts.  AS: v [F][N][J], lam [F][J][I], P_or_R = P [F][I][I].
  * EM: v [F][N][J], lam ignored (may be NULL), P_or_R = S [F][J][I][I].

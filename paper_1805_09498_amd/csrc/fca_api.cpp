@@ -482,6 +482,16 @@ fca_status fca_loglik(fca_ctx* c, double* out) {
   return FCA_OK;
 }
 
+fca_status fca_loglik_device(fca_ctx* c, double* out_dev) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!out_dev || !aligned(out_dev, 8)) return fail(c, FCA_ERR_ARG, "out_dev must be an 8-byte aligned device pointer");
+  hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_loglik(c->s, c->stream) : c->ks->em_loglik(c->s, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "log-likelihood");
+  if ((e = hipMemcpyAsync(out_dev, c->s.ll, sizeof(double), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "hipMemcpyAsync");
+  return FCA_OK;
+}
+
 fca_status fca_get_params(fca_ctx* c, float* v, float* lam, fca_c64* P_or_R) {
   if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
   if ((v && !aligned(v, 4)) || (lam && !aligned(lam, 4)) || (P_or_R && !aligned(P_or_R, 8)))

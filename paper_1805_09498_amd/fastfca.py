@@ -3,7 +3,7 @@ step of FCA / FastFCA-AS runs in the library's HIP kernels.
 
 The functions carry the names of the C ABI (include/fastfca.h):
 ``fca_init``, ``fastfca_as_iterate``, ``fca_em_iterate``,
-``fca_wiener_separate``, ``fca_loglik``, ``fca_get_params``,
+``fca_wiener_separate``, ``fca_loglik``, ``fca_loglik_device``, ``fca_get_params``,
 ``fca_set_params``, ``fca_set_option``, ``fca_get_option``, ``fca_last_error``,
 ``fca_destroy``, the batch calls ``fca_batch_*`` and the derivative calls
 ``fastfca_as_forward`` / ``fastfca_as_backward`` (``autograd.py`` wraps them
@@ -35,7 +35,7 @@ FCA_METHOD_AS = 0
 FCA_METHOD_EM = 1
 
 EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
-            "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
+            "fca_loglik", "fca_loglik_device", "fca_get_params", "fca_set_params", "fca_set_option",
             "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
             "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
             "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
@@ -57,6 +57,8 @@ def _load():
     lib.fca_wiener_separate.restype = i
     lib.fca_loglik.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.fca_loglik.restype = i
+    lib.fca_loglik_device.argtypes = [vp, vp]
+    lib.fca_loglik_device.restype = i
     lib.fca_get_params.argtypes = [vp, vp, vp, vp]
     lib.fca_get_params.restype = i
     lib.fca_set_params.argtypes = [vp, vp, vp, vp]
@@ -200,6 +202,16 @@ def fca_loglik(ctx):
     out = ctypes.c_double()
     _check(lib.fca_loglik(ctx.handle, ctypes.byref(out)), ctx)
     return out.value
+
+
+def fca_loglik_device(ctx, out=None):
+    """Enqueues the log-likelihood into a one-element float64 device tensor
+    (allocated if not given) without synchronising; returns the tensor."""
+    if out is None:
+        with torch.cuda.stream(ctx.stream):
+            out = torch.empty((1,), dtype=torch.float64, device="cuda")
+    _check(lib.fca_loglik_device(ctx.handle, _ptr(out, torch.float64, (1,), "out")), ctx)
+    return out
 
 
 def fca_get_params(ctx):

@@ -44,7 +44,7 @@ def lib():
 def test_header_declares_the_expected_calls():
     assert declared_functions() == sorted([
         "fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
-        "fca_loglik", "fca_get_params", "fca_set_params", "fca_set_option",
+        "fca_loglik", "fca_loglik_device", "fca_get_params", "fca_set_params", "fca_set_option",
         "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
         "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
         "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
@@ -54,6 +54,12 @@ def test_header_declares_the_expected_calls():
 def test_every_declared_function_is_exported(lib):
     for name in declared_functions():
         assert hasattr(lib, name), name
+
+
+def test_loglik_device_rejects_a_null_context_on_the_host(lib):
+    lib.fca_loglik_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.fca_loglik_device.restype = ctypes.c_int
+    assert lib.fca_loglik_device(None, FAKE) == -1
 
 
 FAKE = 0x10000  # aligned, never dereferenced: every case below fails validation first

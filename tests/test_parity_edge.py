@@ -66,6 +66,31 @@ def test_loglik_and_wiener_edge(ff, I, J, F, N):
     assert rel(s, oracle.wiener_as(p.x, v, lam, P)) <= TOL_PARAM
 
 
+@pytest.mark.parametrize("method", ["as", "em"])
+def test_loglik_device_matches_the_host_call(ff, method):
+    """fca_loglik_device queues the same sum as fca_loglik into device memory
+    without a host round trip: two queued values (after 1 and after 3
+    iterations) equal the synchronous calls bitwise; a NULL destination is an
+    argument error."""
+    import torch
+    p = problem(3, 3, 6, 130, seed=55)
+    t = to_dev(p)
+    m = ff.FCA_METHOD_AS if method == "as" else ff.FCA_METHOD_EM
+    iterate = ff.fastfca_as_iterate if method == "as" else ff.fca_em_iterate
+    ctx = ff.fca_init(m, t["x"], t["v0"], t["lam0"], t["P0"])
+    iterate(ctx, 1)
+    a = ff.fca_loglik_device(ctx)
+    ref_a = ff.fca_loglik(ctx)
+    iterate(ctx, 2)
+    b = torch.empty((1,), dtype=torch.float64, device="cuda")
+    ff.fca_loglik_device(ctx, b)
+    ref_b = ff.fca_loglik(ctx)
+    torch.cuda.synchronize()
+    assert float(a.item()) == ref_a and float(b.item()) == ref_b
+    assert ref_a != ref_b
+    assert ff.lib.fca_loglik_device(ctx.handle, None) == ff.FCA_ERR_ARG
+
+
 @pytest.mark.parametrize("J", [1, 2, 3])
 def test_long_run_ragged_frames_stay_finite(ff, J):
     """Lanes past N (padding) must stay finite over long in-kernel runs: 300
