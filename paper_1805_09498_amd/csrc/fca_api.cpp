@@ -485,10 +485,10 @@ fca_status fca_loglik(fca_ctx* c, double* out) {
 fca_status fca_loglik_device(fca_ctx* c, double* out_dev) {
   if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
   if (!out_dev || !aligned(out_dev, 8)) return fail(c, FCA_ERR_ARG, "out_dev must be an 8-byte aligned device pointer");
-  hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_loglik(c->s, c->stream) : c->ks->em_loglik(c->s, c->stream);
+  DevState s = c->s;
+  s.ll = out_dev;  // the final sum writes the caller's double directly
+  hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_loglik(s, c->stream) : c->ks->em_loglik(s, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "log-likelihood");
-  if ((e = hipMemcpyAsync(out_dev, c->s.ll, sizeof(double), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
-    return hip_fail(c, e, "hipMemcpyAsync");
   return FCA_OK;
 }
 
@@ -519,15 +519,14 @@ fca_status fca_set_params(fca_ctx* c, const float* v, const float* lam, const fc
   hipError_t e = hipSuccess;
   ++c->version;
   if (v) e = fca::launch_pack_v(v, s.vs, c->F, c->N, c->J, s.Npad, c->stream);
-  if (e == hipSuccess && lam && c->method == FCA_METHOD_AS)
-    e = hipMemcpyAsync(s.lam, lam, sizeof(float) * c->F * c->J * c->I, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess && P_or_R) {
-    if (c->method == FCA_METHOD_AS) {
-      e = hipMemcpyAsync(s.P, P_or_R, sizeof(float2) * c->F * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
-    } else {
-      e = hipMemcpyAsync(s.R, P_or_R, sizeof(float2) * c->F * c->J * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
-      if (e == hipSuccess) e = c->ks->em_rinv(s, c->stream);
-    }
+  if (e == hipSuccess && c->method == FCA_METHOD_AS && (lam || P_or_R)) {
+    // lambda and P in one launch (a NULL one is skipped)
+    e = fca::launch_copy3(s.lam, lam, lam ? (long long)c->F * c->J * c->I : 0, reinterpret_cast<float*>(s.P),
+                          reinterpret_cast<const float*>(P_or_R), P_or_R ? 2LL * c->F * c->I * c->I : 0, nullptr,
+                          nullptr, 0, c->stream);
+  } else if (e == hipSuccess && P_or_R && c->method == FCA_METHOD_EM) {
+    e = hipMemcpyAsync(s.R, P_or_R, sizeof(float2) * c->F * c->J * c->I * c->I, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = c->ks->em_rinv(s, c->stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "fca_set_params");
   return FCA_OK;

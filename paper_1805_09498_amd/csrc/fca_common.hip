@@ -73,11 +73,12 @@ __global__ void k_check_finite(const float* __restrict__ a, long long n, int* fl
   if (bad) atomicOr(flag, 1);
 }
 
-// Deterministic sum of the per-bin log-likelihoods (one workgroup).
-__global__ void k_sum_f(const double* __restrict__ llf, int F, double* out) {
+// Deterministic sum of n doubles (the log-likelihood partials of every
+// tile), one workgroup in a fixed order.
+__global__ void k_sum_f(const double* __restrict__ part, int n, double* out) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int f = threadIdx.x; f < F; f += blockDim.x) acc += llf[f];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) acc += part[k];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int m = 128; m > 0; m >>= 1) {

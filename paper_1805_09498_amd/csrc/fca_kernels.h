@@ -542,33 +542,23 @@ __global__ __launch_bounds__(kBlock) void k_as_loglik(DevState s) {
       acc += (double)t;
     }
   }
+  if (chunk == 0 && threadIdx.x == 0) {  // the bin's N (2 ln|det P| - I ln pi), once
+    float Mr[I][I], Mi[I][I];
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) { Mr[a][b] = sP[a * I + b].x; Mi[a][b] = sP[a * I + b].y; }
+    const double lad = (double)lu_logabsdet<I>(Mr, Mi);
+    acc += (double)s.N * (2.0 * lad - (double)I * 1.1447298858494002);
+  }
   block_sum_store_d(acc, s.partL + (size_t)f * s.nchunk + chunk, red);
 }
 
-// Per bin: sum of the tiles + N (2 ln|det P| - I ln pi).
-template <int I>
-__global__ __launch_bounds__(64) void k_as_loglik_bin(DevState s) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= s.F) return;
-  float Mr[I][I], Mi[I][I];
-#pragma unroll
-  for (int a = 0; a < I; ++a)
-#pragma unroll
-    for (int b = 0; b < I; ++b) {
-      const float2 t = s.P[(size_t)f * I * I + a * I + b];
-      Mr[a][b] = t.x; Mi[a][b] = t.y;
-    }
-  const double lad = (double)lu_logabsdet<I>(Mr, Mi);
-  double acc = 0.0;
-  for (int c = 0; c < s.nchunk; ++c) acc += s.partL[(size_t)f * s.nchunk + c];
-  s.llf[f] = acc + (double)s.N * (2.0 * lad - (double)I * 1.1447298858494002);
-}
-
+// L2 = the sum of all tiles' partials (one workgroup, fixed order) into s.ll.
 template <int I, int J>
 hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
   hipLaunchKernelGGL((k_as_loglik<I, J>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s);
-  hipLaunchKernelGGL((k_as_loglik_bin<I>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
-  return launch_sum_f(s.llf, s.F, s.ll, st);
+  return launch_sum_f(s.partL, s.F * s.nchunk, s.ll, st);
 }
 
 // ----------------------------------------------------------------------------
@@ -600,8 +590,22 @@ __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __rest
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float2 sP[I * I], sB[I * I];
   __shared__ float sLam[J * I];
-  for (int t = threadIdx.x; t < I * I; t += kBlock) { sP[t] = s.P[(size_t)f * I * I + t]; sB[t] = s.Bm[(size_t)f * I * I + t]; }
+  for (int t = threadIdx.x; t < I * I; t += kBlock) sP[t] = s.P[(size_t)f * I * I + t];
   for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
+  __syncthreads();
+  if (threadIdx.x < I) {  // B = P^-H, lane c solves P^H b = e_c for column c
+    const int c = threadIdx.x;
+    float Mr[I][I], Mi[I][I], br[I], bi[I];
+#pragma unroll
+    for (int r = 0; r < I; ++r)
+#pragma unroll
+      for (int k = 0; k < I; ++k) { Mr[r][k] = sP[k * I + r].x; Mi[r][k] = -sP[k * I + r].y; }
+#pragma unroll
+    for (int r = 0; r < I; ++r) { br[r] = (r == c) ? 1.f : 0.f; bi[r] = 0.f; }
+    lu_solve<I>(Mr, Mi, br, bi);
+#pragma unroll
+    for (int r = 0; r < I; ++r) sB[r * I + c] = make_float2(br[r], bi[r]);
+  }
   __syncthreads();
   float Pr[I][I], Pi[I][I], Br[I][I], Bi[I][I], lam[J][I];
   load_P<I>(sP, Pr, Pi);
@@ -654,7 +658,6 @@ __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __rest
 
 template <int I, int J>
 hipError_t launch_as_wiener(const DevState& s, hipStream_t st, float2* out) {
-  hipLaunchKernelGGL((k_p_inv_herm<I>), dim3((s.F * I + 63) / 64), dim3(64), 0, st, s);
   hipLaunchKernelGGL((k_as_wiener<I, J>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s, out);
   return hipGetLastError();
 }
@@ -987,23 +990,15 @@ __global__ __launch_bounds__(kBlock) void k_em_loglik(DevState s) {
     }
     acc = (double)t;
   }
+  if (chunk == 0 && threadIdx.x == 0) acc -= (double)s.N * (double)I * 1.1447298858494002;  // the bin's -N I ln pi
   block_sum_store_d(acc, s.partL + (size_t)f * s.nchunk_em + chunk, red);
 }
 
-template <int I>
-__global__ __launch_bounds__(64) void k_em_loglik_bin(DevState s) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= s.F) return;
-  double acc = 0.0;
-  for (int c = 0; c < s.nchunk_em; ++c) acc += s.partL[(size_t)f * s.nchunk_em + c];
-  s.llf[f] = acc - (double)s.N * (double)I * 1.1447298858494002;
-}
-
+// L1 = the sum of all tiles' partials (one workgroup, fixed order) into s.ll.
 template <int I, int J>
 hipError_t launch_em_loglik(const DevState& s, hipStream_t st) {
   hipLaunchKernelGGL((k_em_loglik<I, J>), dim3(s.nchunk_em, s.F), dim3(kBlock), 0, st, s);
-  hipLaunchKernelGGL((k_em_loglik_bin<I>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
-  return launch_sum_f(s.llf, s.F, s.ll, st);
+  return launch_sum_f(s.partL, s.F * s.nchunk_em, s.ll, st);
 }
 
 // x_j = v_j S_j C^-1 x (eq. 3).
