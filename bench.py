@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--bins-per-wg", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--path", type=int, default=0)
+    ap.add_argument("--split-streams", type=int, default=0,
+                    help="streaming FastFCA-AS: streams the bins are split over (1..4; 0 = library default)")
     ap.add_argument("--em-steps", type=int, default=3)
     ap.add_argument("--no-em", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -287,6 +289,8 @@ def main():
             ff.fca_set_option(ctx, "bins_per_wg", args.bins_per_wg)
             ff.fca_set_option(ctx, "path", args.path)
             ff.fca_set_option(ctx, "autotune", args.autotune)
+            if args.split_streams:
+                ff.fca_set_option(ctx, "split_streams", args.split_streams)
             iterate = ff.fastfca_as_iterate
             reset = (v0, lam0, P0)
         else:

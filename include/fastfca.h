@@ -147,7 +147,10 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * forced by the options above, the first iterate call of a context times
  * every launch shape that fits on a saved copy of the state, restores it and
  * caches the fastest for the process under (method, I, J, F, N, K); this call
- * synchronises the stream.  0 = fixed preference order).  When the
+ * synchronises the stream.  0 = fixed preference order), "split_streams"
+ * (FastFCA-AS on the streaming kernels: the bins are split into this many
+ * parts, 1..4, default 2, that iterate on the context's stream and on
+ * streams the library owns, forked and joined with events; 1 = one stream).  When the
  * environment variable FASTFCA_TUNE_CACHE names a writable file, measured
  * shapes are also appended to it and read back by later processes (keyed by
  * GPU architecture, compute-unit count and library build; unreadable or
@@ -164,7 +167,7 @@ fca_status fca_set_option_f64(fca_ctx *ctx, const char *key, double value);
 fca_status fca_get_option_f64(fca_ctx *ctx, const char *key, double *value);
 
 /* Read an option ("K", "p_update", "check_finite", "path", "waves", "bins_per_wg",
- * "autotune": the configured values) or the launch shape the last iterate
+ * "autotune", "split_streams": the configured values) or the launch shape the last iterate
  * call used ("last_waves": waves per workgroup, 0 = streaming kernels, -1 =
  * no call yet; "last_bins_per_wg").  value is a host pointer.  Unknown keys
  * give FCA_ERR_ARG. */

@@ -92,7 +92,76 @@ bool shape_fits(const fca_ctx* c, Shape sh) {
                                     : (sh.bpw == 1 && c->ks->em_resident_fits(c->N, sh.waves) != 0);
 }
 
+// Bins f0 .. f0 + nf - 1 of a FastFCA-AS context as a problem of their own:
+// every array the streaming iteration touches is bin-major.
+DevState bin_view(const fca_ctx* c, int f0, int nf) {
+  const DevState& s = c->s;
+  const size_t f = (size_t)f0, I = c->I, J = c->J, Np = s.Npad;
+  DevState v = s;
+  v.F = nf;
+  v.xs = s.xs + f * 2 * I * Np;
+  v.vs = s.vs + f * J * Np;
+  v.lam = s.lam + f * J * I;
+  v.P = s.P + f * I * I;
+  v.Bm = s.Bm + f * I * I;
+  v.partA = s.partA + f * s.nchunk * J * I;
+  v.partB = s.partB + f * s.nchunk * I * I * I;
+  v.partL = s.partL + f * (s.nchunk > s.nchunk_em ? s.nchunk : s.nchunk_em);
+  v.llf = s.llf + f;
+  return v;
+}
+
+// The split's streams and events, created once per context (default
+// priority, non-blocking).
+hipError_t ensure_side_streams(fca_ctx* c) {
+  if (c->side[0]) return hipSuccess;
+  hipStream_t st[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&st[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    for (int k = 0; k < 3; ++k) {
+      if (join[k]) (void)hipEventDestroy(join[k]);
+      if (st[k]) (void)hipStreamDestroy(st[k]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    return e;
+  }
+  for (int k = 0; k < 3; ++k) { c->side[k] = st[k]; c->ev_join[k] = join[k]; }
+  c->ev_fork = fork;
+  return hipSuccess;
+}
+
+// Streaming FastFCA-AS iterations with the bins split into c->split parts on
+// as many streams (the bins never interact): one part's HBM-bound pass A can
+// share the CUs with another part's VALU-bound pass B.  Fork and join are
+// events, so the call can be captured into a graph.
+hipError_t launch_stream_split(fca_ctx* c, int n_iter) {
+  hipError_t e = ensure_side_streams(c);
+  if (e != hipSuccess) return e;
+  const int parts = c->split < c->F ? c->split : c->F;
+  if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
+  for (int k = 1; k < parts; ++k)
+    if ((e = hipStreamWaitEvent(c->side[k - 1], c->ev_fork, 0)) != hipSuccess) return e;
+  for (int k = 0; k < parts; ++k) {
+    const int f0 = (int)((long long)c->F * k / parts), f1 = (int)((long long)c->F * (k + 1) / parts);
+    const DevState h = bin_view(c, f0, f1 - f0);
+    hipStream_t st = k == 0 ? c->stream : c->side[k - 1];
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) e = c->ks->as_iter_stream(h, st);
+    if (e != hipSuccess) return e;
+  }
+  for (int k = 1; k < parts; ++k) {
+    if ((e = hipEventRecord(c->ev_join[k - 1], c->side[k - 1])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(c->stream, c->ev_join[k - 1], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_shape(fca_ctx* c, Shape sh, int n_iter) {
+  if (sh.waves == 0 && c->method == FCA_METHOD_AS && c->split > 1 && c->F >= 2) return launch_stream_split(c, n_iter);
   if (sh.waves == 0) {
     for (int it = 0; it < n_iter; ++it) {
       hipError_t e = c->method == FCA_METHOD_AS ? c->ks->as_iter_stream(c->s, c->stream)
@@ -355,6 +424,8 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   c->method = method; c->F = F; c->N = N; c->I = I; c->J = J;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
+  c->split = 2; c->ev_fork = nullptr;
+  for (int k = 0; k < 3; ++k) { c->side[k] = nullptr; c->ev_join[k] = nullptr; }
   c->backup = nullptr; c->arena = nullptr; c->last_waves = -1; c->last_bpw = -1;
   c->version = 0; c->tape = nullptr; c->tape_bytes = 0; c->tape_iters = 0; c->tape_every = 0;
   c->tape_waves = 0; c->tape_bpw = 0; c->tape_last_rec = 0; c->tape_version = ~0ULL;
@@ -558,6 +629,9 @@ fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
   } else if (!std::strcmp(key, "autotune")) {
     if (value != 0 && value != 1) return fail(c, FCA_ERR_ARG, "autotune must be 0 or 1");
     c->autotune = (int)value;
+  } else if (!std::strcmp(key, "split_streams")) {
+    if (value < 1 || value > 4) return fail(c, FCA_ERR_ARG, "split_streams must be in 1..4");
+    c->split = (int)value;
   } else {
     return fail(c, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
   }
@@ -574,6 +648,7 @@ fca_status fca_get_option(fca_ctx* c, const char* key, long long* value) {
   else if (!std::strcmp(key, "waves")) *value = c->waves;
   else if (!std::strcmp(key, "bins_per_wg")) *value = c->bpw;
   else if (!std::strcmp(key, "autotune")) *value = c->autotune;
+  else if (!std::strcmp(key, "split_streams")) *value = c->split;
   else if (!std::strcmp(key, "last_waves")) *value = c->last_waves;
   else if (!std::strcmp(key, "last_bins_per_wg")) *value = c->last_bpw;
   else return fail(c, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
@@ -608,6 +683,14 @@ const char* fca_last_error(const fca_ctx* c) {
 void fca_destroy(fca_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->side[0]) {
+    for (int k = 0; k < 3; ++k) {
+      (void)hipStreamSynchronize(c->side[k]);
+      (void)hipEventDestroy(c->ev_join[k]);
+      (void)hipStreamDestroy(c->side[k]);
+    }
+    (void)hipEventDestroy(c->ev_fork);
+  }
   if (c->arena) (void)hipFree(c->arena);
   if (c->tape) (void)hipFree(c->tape);
   delete c;

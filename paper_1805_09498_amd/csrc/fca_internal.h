@@ -20,6 +20,9 @@ struct fca_ctx {
   int waves;  // 0 auto
   int bpw;    // bins per workgroup of the resident AS kernel, 0 auto
   int autotune;  // 1: time the candidate launch shapes once per (method, I, J, F, N)
+  int split;     // streams over which streaming FastFCA-AS iterations split the bins (1..4)
+  hipStream_t side[3];          // the split's extra streams (created on first use)
+  hipEvent_t ev_fork, ev_join[3];
   float* backup;  // state copy used while tuning: vs, lam, P (AS) or vs, R (EM)
   int last_waves, last_bpw;  // launch shape of the last iterate call (waves 0: streaming)
   unsigned long long version;  // bumped by every call that changes the state

@@ -91,6 +91,31 @@ def test_loglik_device_matches_the_host_call(ff, method):
     assert ff.lib.fca_loglik_device(ctx.handle, None) == ff.FCA_ERR_ARG
 
 
+@pytest.mark.parametrize("I,J,F,N", [(3, 3, 5, 1100), (6, 4, 7, 300), (2, 2, 1, 70)])
+def test_split_streams_same_bits(ff, I, J, F, N):
+    """The streaming iterations with the bins split over 2, 3 or 4 streams
+    give the same bits as on one stream, the bins being independent (F not a
+    multiple of the parts, fewer bins than parts, F = 1), and match the oracle
+    after one iteration."""
+    p = problem(I, J, F, N, seed=500 + 10 * I + F)
+    v_ref, lam_ref, P_ref = oracle_as(p, 1)
+    runs = []
+    for split in (1, 2, 3, 4):
+        t = to_dev(p)
+        ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+        ff.fca_set_option(ctx, "path", 2)
+        ff.fca_set_option(ctx, "split_streams", split)
+        assert ff.fca_get_option(ctx, "split_streams") == split
+        ff.fastfca_as_iterate(ctx, 1)
+        v, lam, P = params(ff, ctx)
+        assert rel(v, v_ref) <= TOL_PARAM and rel(lam, lam_ref) <= TOL_PARAM and rel(P, P_ref) <= TOL_PARAM
+        ff.fastfca_as_iterate(ctx, 4)
+        runs.append(params(ff, ctx))
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("J", [1, 2, 3])
 def test_long_run_ragged_frames_stay_finite(ff, J):
     """Lanes past N (padding) must stay finite over long in-kernel runs: 300
@@ -113,7 +138,8 @@ def test_method_mismatch_and_options(ff):
     with pytest.raises(ff.FcaError) as e:
         ff.fca_em_iterate(ctx, 1)
     assert e.value.status == ff.FCA_ERR_STATE
-    for key, val in [("K", 0), ("K", 65), ("path", 3), ("waves", 3), ("bins_per_wg", 3), ("autotune", 2), ("nope", 1)]:
+    for key, val in [("K", 0), ("K", 65), ("path", 3), ("waves", 3), ("bins_per_wg", 3), ("autotune", 2),
+                     ("split_streams", 0), ("split_streams", 5), ("nope", 1)]:
         with pytest.raises(ff.FcaError) as e:
             ff.fca_set_option(ctx, key, val)
         assert e.value.status == ff.FCA_ERR_ARG
