@@ -26,10 +26,10 @@
 
 namespace fca {
 
-// Lanes per bin.  Up to I = 3 the adjoint kernels fit in 128 VGPRs (four
-// waves per SIMD), so four waves per bin still keep all 513 bins of a
-// 513-bin problem resident at once and halve the frames per lane; above, two
-// waves per bin.
+// Lanes per bin.  Up to I = 3 the adjoint kernels need at most ~160 VGPRs
+// (three waves per SIMD or more), so four waves per bin still keep all 513
+// bins of a 513-bin problem (2052 waves) resident at once and halve the
+// frames per lane; above, two waves per bin.
 template <int I>
 constexpr int kAdjBlock = (I <= 3) ? 256 : 128;
 
@@ -60,13 +60,6 @@ __device__ inline void block_sum_t(const float (&a)[V], float* out, float* red) 
     out[k] = t;
   }
   __syncthreads();
-}
-
-// The bin's x at frame n (split planes) and y = P^H x.
-template <int I>
-__device__ __forceinline__ void adj_load_x(const float* xf, int Npad, int n, float (&xr)[I], float (&xi)[I]) {
-#pragma unroll
-  for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * Npad + n]; xi[i] = xf[(size_t)(I + i) * Npad + n]; }
 }
 
 // Global accesses at a byte offset from a workgroup-uniform base: the base
