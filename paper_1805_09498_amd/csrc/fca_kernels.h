@@ -502,6 +502,11 @@ __device__ inline void block_sum_store_d(double a, double* out, double* lds) {
   }
 }
 
+// Up to I = 4 the bin's ln|det P| (one LU by one lane) is cheap enough to
+// sit in its first tile's workgroup; above, a lane-per-bin kernel forms it.
+template <int I>
+constexpr bool kLoglikDetInTile = (I <= 4);
+
 // Per point: -sum_i ln d_i - sum_i |(P^H x)_i|^2 / d_i   (the n-dependent part of L2).
 template <int I, int J>
 __global__ __launch_bounds__(kBlock) void k_as_loglik(DevState s) {
@@ -542,23 +547,50 @@ __global__ __launch_bounds__(kBlock) void k_as_loglik(DevState s) {
       acc += (double)t;
     }
   }
-  if (chunk == 0 && threadIdx.x == 0) {  // the bin's N (2 ln|det P| - I ln pi), once
-    float Mr[I][I], Mi[I][I];
+  if constexpr (kLoglikDetInTile<I>) {
+    if (chunk == 0 && threadIdx.x == 0) {  // the bin's N (2 ln|det P| - I ln pi), once
+      float Mr[I][I], Mi[I][I];
 #pragma unroll
-    for (int a = 0; a < I; ++a)
+      for (int a = 0; a < I; ++a)
 #pragma unroll
-      for (int b = 0; b < I; ++b) { Mr[a][b] = sP[a * I + b].x; Mi[a][b] = sP[a * I + b].y; }
-    const double lad = (double)lu_logabsdet<I>(Mr, Mi);
-    acc += (double)s.N * (2.0 * lad - (double)I * 1.1447298858494002);
+        for (int b = 0; b < I; ++b) { Mr[a][b] = sP[a * I + b].x; Mi[a][b] = sP[a * I + b].y; }
+      const double lad = (double)lu_logabsdet<I>(Mr, Mi);
+      acc += (double)s.N * (2.0 * lad - (double)I * 1.1447298858494002);
+    }
   }
   block_sum_store_d(acc, s.partL + (size_t)f * s.nchunk + chunk, red);
 }
 
-// L2 = the sum of all tiles' partials (one workgroup, fixed order) into s.ll.
+// Above I = 4: per bin, one lane per bin, the sum of the tiles + N (2 ln|det P| - I ln pi).
+template <int I>
+__global__ __launch_bounds__(64) void k_as_loglik_bin(DevState s) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= s.F) return;
+  float Mr[I][I], Mi[I][I];
+#pragma unroll
+  for (int a = 0; a < I; ++a)
+#pragma unroll
+    for (int b = 0; b < I; ++b) {
+      const float2 t = s.P[(size_t)f * I * I + a * I + b];
+      Mr[a][b] = t.x; Mi[a][b] = t.y;
+    }
+  const double lad = (double)lu_logabsdet<I>(Mr, Mi);
+  double acc = 0.0;
+  for (int c = 0; c < s.nchunk; ++c) acc += s.partL[(size_t)f * s.nchunk + c];
+  s.llf[f] = acc + (double)s.N * (2.0 * lad - (double)I * 1.1447298858494002);
+}
+
+// L2 into s.ll: the tiles' partials, then one workgroup sums them (or, above
+// I = 4, the per-bin totals) in a fixed order.
 template <int I, int J>
 hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
   hipLaunchKernelGGL((k_as_loglik<I, J>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s);
-  return launch_sum_f(s.partL, s.F * s.nchunk, s.ll, st);
+  if constexpr (kLoglikDetInTile<I>) {
+    return launch_sum_f(s.partL, s.F * s.nchunk, s.ll, st);
+  } else {
+    hipLaunchKernelGGL((k_as_loglik_bin<I>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
+    return launch_sum_f(s.llf, s.F, s.ll, st);
+  }
 }
 
 // ----------------------------------------------------------------------------
