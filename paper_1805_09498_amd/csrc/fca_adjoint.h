@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
 
 // ----------------------------------------------------------------------------
 // Adjoint of the Wiener filter s_j = P^-H (g_j o y), g_ji = v_j lambda_ji / d_i
-// (needs B = P^-H in s.Bm).  gout [J][F][N][I]; writes vb_out, lb_out, Pb_out
+// (B = P^-H is formed in the workgroup).  gout [J][F][N][I]; writes vb_out, lb_out, Pb_out
 // and initialises xb.
 // ----------------------------------------------------------------------------
 template <int I, int J>
@@ -512,13 +512,23 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_wiener(DevState s, const f
   __shared__ float sOut[J * I + 4 * I * I];
   __shared__ float red[pad4(J * I + 4 * I * I) * (kB / kWave)];
   const float2* Pf = s.P + (size_t)f * I * I;
-  const float2* Bf = s.Bm + (size_t)f * I * I;
-  for (int t = tid; t < I * I; t += kB) {
-    const float2 b = Bf[t];
-    sBr[t / I][t % I] = b.x; sBi[t / I][t % I] = b.y;
+  if (tid < I) {  // B = P^-H, formed here: lane c solves P^H b = e_c for column c
+    const int c = tid;
+    float Mr[I][I], Mi[I][I], br[I], bi[I];
+#pragma unroll
+    for (int r = 0; r < I; ++r)
+#pragma unroll
+      for (int k = 0; k < I; ++k) {
+        const float2 p = Pf[k * I + r];
+        Mr[r][k] = p.x; Mi[r][k] = -p.y;
+      }
+#pragma unroll
+    for (int r = 0; r < I; ++r) { br[r] = (r == c) ? 1.f : 0.f; bi[r] = 0.f; }
+    lu_solve<I>(Mr, Mi, br, bi);
+#pragma unroll
+    for (int r = 0; r < I; ++r) { sBr[r][c] = br[r]; sBi[r][c] = bi[r]; }
   }
   stage_P_columns<I>(Pf, sPc);
-  stage_P_columns<I>(Bf, sBc);
   for (int t = tid; t < I * PH; t += kB) {
     const int r = t / PH, k = 2 * (t % PH);
     const float2 p0 = Pf[r * I + k];
@@ -526,6 +536,12 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_wiener(DevState s, const f
     sPw[t] = make_float4(p0.x, p0.y, p1.x, p1.y);
   }
   for (int t = tid; t < J * I; t += kB) sL[t] = s.lam[(size_t)f * J * I + t];
+  __syncthreads();
+  for (int t = tid; t < I * PH; t += kB) {  // B by columns, from the solve above
+    const int i = t / PH, k = 2 * (t % PH), k1 = (k + 1) % I;
+    const bool two = k + 1 < I;
+    sBc[t] = make_float4(sBr[k][i], sBi[k][i], two ? sBr[k1][i] : 0.f, two ? sBi[k1][i] : 0.f);
+  }
   __syncthreads();
   const float* xf = s.xs + (size_t)f * 2 * I * Np;
   const float* vf = s.vs + (size_t)f * J * Np;
@@ -669,7 +685,6 @@ hipError_t launch_adj_iter(const DevState& s, const AdjIter& a, hipStream_t st) 
 
 template <int I, int J>
 hipError_t launch_adj_wiener(const DevState& s, const float2* gout, const AdjIter& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_p_inv_herm<I>), dim3((s.F * I + 63) / 64), dim3(64), 0, st, s);
   hipLaunchKernelGGL((k_adj_wiener<I, J>), dim3(s.F), dim3(kAdjBlock<I>), 0, st, s, gout, a);
   return hipGetLastError();
 }

@@ -596,27 +596,6 @@ hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // Wiener filter (eq. 3; AS form x_j = P^-H (g_j o y) from eq. 15-16).
 // ----------------------------------------------------------------------------
-// Bm[f] = P(f)^-H, one lane per (bin, column).
-template <int I>
-__global__ __launch_bounds__(64) void k_p_inv_herm(DevState s) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int f = t / I, c = t % I;
-  if (f >= s.F) return;
-  float Mr[I][I], Mi[I][I], br[I], bi[I];
-#pragma unroll
-  for (int r = 0; r < I; ++r)
-#pragma unroll
-    for (int k = 0; k < I; ++k) {
-      const float2 p = s.P[(size_t)f * I * I + k * I + r];
-      Mr[r][k] = p.x; Mi[r][k] = -p.y;
-    }
-#pragma unroll
-  for (int r = 0; r < I; ++r) { br[r] = (r == c) ? 1.f : 0.f; bi[r] = 0.f; }
-  lu_solve<I>(Mr, Mi, br, bi);
-#pragma unroll
-  for (int r = 0; r < I; ++r) s.Bm[(size_t)f * I * I + r * I + c] = make_float2(br[r], bi[r]);
-}
-
 template <int I, int J>
 __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __restrict__ out) {
   const int f = blockIdx.y, chunk = blockIdx.x;
