@@ -117,6 +117,13 @@ fca_status fca_loglik(fca_ctx *ctx, double *out);
  * FCA_ERR_ARG for a NULL or misaligned out_dev. */
 fca_status fca_loglik_device(fca_ctx *ctx, double *out_dev);
 
+/* The log-likelihood of each frequency bin (the sum over n of eq. 5 / eq. 14
+ * for one f, constant term included), written to out_dev [F] (device
+ * doubles, 8-byte aligned, owned by the caller).  The bins' values add up to
+ * fca_loglik's total up to the order of the FP64 additions.  Asynchronous.
+ * FCA_ERR_ARG for a NULL or misaligned out_dev. */
+fca_status fca_loglik_bins(fca_ctx *ctx, double *out_dev);
+
 /* Copy the current parameters to caller-owned device arrays in the ABI
  * layouts.  AS: v [F][N][J], lam [F][J][I], P_or_R = P [F][I][I].
  * EM: v [F][N][J], lam ignored (may be NULL), P_or_R = S [F][J][I][I].

@@ -164,6 +164,8 @@ fca_status fastfca_as_backward(fca_ctx* c, const fca_c64* grad_out, fca_c64* gra
   if (c->method != FCA_METHOD_AS) return fca::ctx_fail(c, FCA_ERR_STATE, "fastfca_as_backward on an FCA EM context");
   if (!c->tape || c->tape_version != c->version)
     return fca::ctx_fail(c, FCA_ERR_STATE, "no recorded forward run matches the current state");
+  if (c->s.K != 1 || c->s.p_update != 0)
+    return fca::ctx_fail(c, FCA_ERR_STATE, "the P-step options changed after the recorded forward run");
   if (!grad_out || !aligned(grad_out, 8) || (grad_x && !aligned(grad_x, 8)) || (grad_P0 && !aligned(grad_P0, 8)) ||
       (grad_v0 && !aligned(grad_v0, 4)) || (grad_lam0 && !aligned(grad_lam0, 4)))
     return fca::ctx_fail(c, FCA_ERR_ARG, "grad_out must be non-NULL; misaligned pointer");

@@ -103,7 +103,6 @@ DevState bin_view(const fca_ctx* c, int f0, int nf) {
   v.vs = s.vs + f * J * Np;
   v.lam = s.lam + f * J * I;
   v.P = s.P + f * I * I;
-  v.Bm = s.Bm + f * I * I;
   v.partA = s.partA + f * s.nchunk * J * I;
   v.partB = s.partB + f * s.nchunk * I * I * I;
   v.partL = s.partL + f * (s.nchunk > s.nchunk_em ? s.nchunk : s.nchunk_em);
@@ -441,7 +440,6 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   const size_t o_vs = a.take<float>((size_t)F * J * Npad);
   const size_t o_lam = a.take<float>(FJI);
   const size_t o_P = a.take<float2>(FII);
-  const size_t o_Bm = a.take<float2>(FII);
   const bool em = method == FCA_METHOD_EM;
   const size_t o_R = em ? a.take<float2>(FJII) : 0;
   const size_t o_Ri = em ? a.take<float2>(FJII) : 0;
@@ -466,7 +464,6 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   s.vs = reinterpret_cast<float*>(base + o_vs);
   s.lam = reinterpret_cast<float*>(base + o_lam);
   s.P = reinterpret_cast<float2*>(base + o_P);
-  s.Bm = reinterpret_cast<float2*>(base + o_Bm);
   s.R = em ? reinterpret_cast<float2*>(base + o_R) : nullptr;
   s.Rinv = em ? reinterpret_cast<float2*>(base + o_Ri) : nullptr;
   s.partA = reinterpret_cast<float*>(base + o_pA);
@@ -563,6 +560,22 @@ fca_status fca_loglik_device(fca_ctx* c, double* out_dev) {
   return FCA_OK;
 }
 
+fca_status fca_loglik_bins(fca_ctx* c, double* out_dev) {
+  if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
+  if (!out_dev || !aligned(out_dev, 8)) return fail(c, FCA_ERR_ARG, "out_dev must be an 8-byte aligned device pointer");
+  const DevState& s = c->s;
+  const bool as = c->method == FCA_METHOD_AS;
+  hipError_t e = as ? c->ks->as_loglik(s, c->stream) : c->ks->em_loglik(s, c->stream);
+  if (e == hipSuccess) {
+    if (as && c->I > fca::kLoglikDetInTileMaxI)
+      e = hipMemcpyAsync(out_dev, s.llf, sizeof(double) * c->F, hipMemcpyDeviceToDevice, c->stream);
+    else
+      e = fca::launch_sum_chunks(s.partL, c->F, as ? s.nchunk : s.nchunk_em, out_dev, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "per-bin log-likelihood");
+  return FCA_OK;
+}
+
 fca_status fca_get_params(fca_ctx* c, float* v, float* lam, fca_c64* P_or_R) {
   if (!c) return fail(nullptr, FCA_ERR_ARG, "NULL context");
   if ((v && !aligned(v, 4)) || (lam && !aligned(lam, 4)) || (P_or_R && !aligned(P_or_R, 8)))
@@ -608,10 +621,12 @@ fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
   if (!key) return fail(c, FCA_ERR_ARG, "NULL key");
   if (!std::strcmp(key, "K")) {
     if (value < 1 || value > 64) return fail(c, FCA_ERR_ARG, "K must be in 1..64");
+    if (c->s.K != (int)value) ++c->version;  // a recorded forward run no longer describes the iteration
     c->s.K = (int)value;
   } else if (!std::strcmp(key, "p_update")) {
     if (value < 0 || value > 2) return fail(c, FCA_ERR_ARG, "p_update must be 0 (fixed point), 1 (gradient) or 2 (natural gradient)");
     if (c->method != FCA_METHOD_AS && value != 0) return fail(c, FCA_ERR_STATE, "p_update applies to FastFCA-AS contexts");
+    if (c->s.p_update != (int)value) ++c->version;
     c->s.p_update = (int)value;
   } else if (!std::strcmp(key, "check_finite")) {
     if (value != 0 && value != 1) return fail(c, FCA_ERR_ARG, "check_finite must be 0 or 1");
@@ -660,6 +675,7 @@ fca_status fca_set_option_f64(fca_ctx* c, const char* key, double value) {
   if (!key) return fail(c, FCA_ERR_ARG, "NULL key");
   if (!std::strcmp(key, "p_step")) {
     if (!(value > 0.0 && value <= 1e3)) return fail(c, FCA_ERR_ARG, "p_step must be in (0, 1000]");
+    if (c->s.p_step != (float)value) ++c->version;
     c->s.p_step = (float)value;
   } else {
     return fail(c, FCA_ERR_ARG, std::string("unknown real option '") + key + "'");

@@ -88,6 +88,16 @@ __global__ void k_sum_f(const double* __restrict__ part, int n, double* out) {
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// Per-bin totals of per-tile partials: out[f] = sum_c part[f * nchunk + c],
+// in tile order (one lane per bin).
+__global__ void k_sum_chunks(const double* __restrict__ part, int F, int nchunk, double* __restrict__ out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += part[(size_t)f * nchunk + c];
+  out[f] = acc;
+}
+
 static unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipError_t launch_pack_x(const float2* x, float* xs, int F, int N, int I, int Npad, hipStream_t st) {
@@ -127,6 +137,10 @@ hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream
 }
 hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, st, llf, F, out);
+  return hipGetLastError();
+}
+hipError_t launch_sum_chunks(const double* part, int F, int nchunk, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_chunks, dim3(blocks_for(F, 64)), dim3(64), 0, st, part, F, nchunk, out);
   return hipGetLastError();
 }
 

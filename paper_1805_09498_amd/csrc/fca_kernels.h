@@ -505,7 +505,7 @@ __device__ inline void block_sum_store_d(double a, double* out, double* lds) {
 // Up to I = 4 the bin's ln|det P| (one LU by one lane) is cheap enough to
 // sit in its first tile's workgroup; above, a lane-per-bin kernel forms it.
 template <int I>
-constexpr bool kLoglikDetInTile = (I <= 4);
+constexpr bool kLoglikDetInTile = (I <= kLoglikDetInTileMaxI);
 
 // Per point: -sum_i ln d_i - sum_i |(P^H x)_i|^2 / d_i   (the n-dependent part of L2).
 template <int I, int J>

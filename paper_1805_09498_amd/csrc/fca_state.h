@@ -15,6 +15,10 @@ constexpr int kChunkEm = kBlock;  // FCA EM: one point per lane
 // fixed-point steps or the gradient P step (both need the inverse of a
 // matrix per lane); larger I with either uses the streaming kernels.
 constexpr int kResMaxIK = 4;
+// Largest I whose FastFCA-AS log-likelihood adds the bin's ln|det P| term in
+// the first tile's workgroup; above, a lane-per-bin kernel writes per-bin
+// totals into llf.
+constexpr int kLoglikDetInTileMaxI = 4;
 
 // Internal layouts (library-owned):
 //   xs   [F][2I][Npad]  split-complex mixture: plane i = Re x_i, plane I+i = Im x_i
@@ -35,7 +39,6 @@ struct DevState {
   float2* P;
   float2* R;
   float2* Rinv;
-  float2* Bm;     // scratch [F][I][I]
   float* partA;   // scratch per-tile partial sums
   float* partB;
   double* partL;  // [F][max(nchunk, nchunk_em)]
@@ -106,6 +109,7 @@ hipError_t launch_unpack_v(const float* vs, float* v, int F, int N, int J, int N
 hipError_t launch_unpack_x(const float* xs, float2* x, int F, int N, int I, int Npad, hipStream_t st);
 hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream_t st);
 hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st);
+hipError_t launch_sum_chunks(const double* part, int F, int nchunk, double* out, hipStream_t st);
 
 const KernelSet* kernel_set(int I, int J);  // NULL if not instantiated
 

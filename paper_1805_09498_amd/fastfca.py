@@ -3,7 +3,8 @@ step of FCA / FastFCA-AS runs in the library's HIP kernels.
 
 The functions carry the names of the C ABI (include/fastfca.h):
 ``fca_init``, ``fastfca_as_iterate``, ``fca_em_iterate``,
-``fca_wiener_separate``, ``fca_loglik``, ``fca_loglik_device``, ``fca_get_params``,
+``fca_wiener_separate``, ``fca_loglik``, ``fca_loglik_device``, ``fca_loglik_bins``,
+``fca_get_params``,
 ``fca_set_params``, ``fca_set_option``, ``fca_get_option``, ``fca_last_error``,
 ``fca_destroy``, the batch calls ``fca_batch_*`` and the derivative calls
 ``fastfca_as_forward`` / ``fastfca_as_backward`` (``autograd.py`` wraps them
@@ -35,7 +36,7 @@ FCA_METHOD_AS = 0
 FCA_METHOD_EM = 1
 
 EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
-            "fca_loglik", "fca_loglik_device", "fca_get_params", "fca_set_params", "fca_set_option",
+            "fca_loglik", "fca_loglik_device", "fca_loglik_bins", "fca_get_params", "fca_set_params", "fca_set_option",
             "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
             "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
             "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
@@ -59,6 +60,8 @@ def _load():
     lib.fca_loglik.restype = i
     lib.fca_loglik_device.argtypes = [vp, vp]
     lib.fca_loglik_device.restype = i
+    lib.fca_loglik_bins.argtypes = [vp, vp]
+    lib.fca_loglik_bins.restype = i
     lib.fca_get_params.argtypes = [vp, vp, vp, vp]
     lib.fca_get_params.restype = i
     lib.fca_set_params.argtypes = [vp, vp, vp, vp]
@@ -211,6 +214,16 @@ def fca_loglik_device(ctx, out=None):
         with torch.cuda.stream(ctx.stream):
             out = torch.empty((1,), dtype=torch.float64, device="cuda")
     _check(lib.fca_loglik_device(ctx.handle, _ptr(out, torch.float64, (1,), "out")), ctx)
+    return out
+
+
+def fca_loglik_bins(ctx, out=None):
+    """Enqueues the per-bin log-likelihood into a float64 device tensor [F]
+    (allocated if not given) without synchronising; returns the tensor."""
+    if out is None:
+        with torch.cuda.stream(ctx.stream):
+            out = torch.empty((ctx.F,), dtype=torch.float64, device="cuda")
+    _check(lib.fca_loglik_bins(ctx.handle, _ptr(out, torch.float64, (ctx.F,), "out")), ctx)
     return out
 
 
@@ -403,3 +416,4 @@ def fca_istft(S, L, frame=1024, hop=512, stream=None):
     _check(lib.fca_istft(_ptr(S, torch.complex64, (J, F, N, C), "S"), J, C, N, int(frame), int(hop), int(L),
                          ctypes.c_void_p(wav.data_ptr()), sh))
     return wav
+

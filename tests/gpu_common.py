@@ -1,12 +1,24 @@
 """Helpers of the GPU parity tests: move a seeded problem to the device, run
 the library through the C ABI, compare with the FP64 oracle.
 
-Tolerances: per-tensor relative Frobenius error |a - b| / |b| <= 1e-4 for
-v, lambda, P (or S) after one iteration; <= 1e-5 relative on the
-log-likelihood after ten iterations.  The oracle always runs on the
-single-precision-rounded inputs widened to FP64, so input rounding is not
-charged to the GPU.
+Two kinds of bounds are asserted:
+
+* per tensor, the relative Frobenius error |a - b| / |b| <= 1e-4 for v,
+  lambda, P (or S) after one iteration and <= 1e-5 relative on the
+  log-likelihood after ten iterations;
+* per entry, |a - b| <= a first-order bound on the rounding error of the
+  single-precision evaluation, computed in FP64 from the state the step
+  starts from (tests/error_bounds.py; for P it scales with the condition
+  number of each eq. 23 matrix).
+
+``check`` also reports the worst per-bin relative error and the largest
+elementwise relative error over the entries above 1e-6 of their bin's
+largest magnitude.  The oracle always runs on the single-precision-rounded
+inputs widened to FP64, so input rounding is not charged to the GPU.
 """
+
+import json
+import os
 
 import numpy as np
 import torch
@@ -16,11 +28,66 @@ from paper_1805_09498_amd import synth
 
 TOL_PARAM = 1e-4
 TOL_LOGLIK = 1e-5
+ELEM_FLOOR = 1e-6
 
 
 def rel(a, b):
     a = np.asarray(a); b = np.asarray(b)
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def per_bin_rel(a, b, axis=0):
+    """The largest relative Frobenius error over the bins (axis `axis`)."""
+    a = np.moveaxis(np.asarray(a), axis, 0)
+    b = np.moveaxis(np.asarray(b), axis, 0)
+    F = b.shape[0]
+    num = np.linalg.norm((a - b).reshape(F, -1), axis=1)
+    den = np.linalg.norm(b.reshape(F, -1), axis=1)
+    return float(np.max(num / np.where(den > 0, den, 1.0)))
+
+
+def elem_rel(a, b, axis=0, floor=ELEM_FLOOR):
+    """The largest |a - b| / |b| over the entries with |b| above `floor` times
+    the largest |b| of their bin (axis `axis`)."""
+    a = np.moveaxis(np.asarray(a), axis, 0)
+    b = np.moveaxis(np.asarray(b), axis, 0)
+    F = b.shape[0]
+    ab = np.abs(b).reshape(F, -1)
+    err = np.abs(a - b).reshape(F, -1)
+    keep = ab > floor * ab.max(axis=1, keepdims=True)
+    if not keep.any():
+        return 0.0
+    return float(np.max(err[keep] / ab[keep]))
+
+
+def check(name, got, ref, bound=None, tol=None, axis=0, bin_tol=None):
+    """Compare a HIP result with the oracle's: every entry within `bound`
+    (absolute, broadcastable to `ref`), the tensor within `tol` (relative
+    Frobenius) and every bin (axis `axis`) within `bin_tol` (relative
+    Frobenius per bin), whichever are given.  Returns the measures; when
+    FASTFCA_PARITY_LOG names a file they are appended to it as a JSON line."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
+    assert np.isfinite(got).all(), f"{name}: non-finite entries"
+    m = {"name": name, "rel": rel(got, ref), "bin_rel": per_bin_rel(got, ref, axis),
+         "elem_rel": elem_rel(got, ref, axis)}
+    if bound is not None:
+        bound = np.broadcast_to(np.asarray(bound, np.float64), ref.shape)
+        err = np.abs(got - ref)
+        m["err_over_bound"] = float(np.max(err / np.where(bound > 0, bound, np.inf))) if err.size else 0.0
+    log = os.environ.get("FASTFCA_PARITY_LOG")
+    if log:
+        with open(log, "a") as fh:
+            fh.write(json.dumps(m) + "\n")
+    print("parity", json.dumps(m))
+    if bound is not None:
+        assert np.all(err <= bound), f"{name}: error above the rounding bound {m}"
+    if tol is not None:
+        assert m["rel"] <= tol, f"{name}: relative error above {tol} {m}"
+    if bin_tol is not None:
+        assert m["bin_rel"] <= bin_tol, f"{name}: a bin's relative error above {bin_tol} {m}"
+    return m
 
 
 def problem(I, J, F, N, seed, **kw):
@@ -64,6 +131,47 @@ def oracle_as(p, n_iter, K=1):
     for _ in range(n_iter):
         v, lam, P = oracle.fastfca_as_step(p.x, v, lam, P, K=K)
     return v, lam, P
+
+
+def oracle_as_bounded(p, n_iter, K=1, p_update=0, mu=0.1):
+    """The oracle's (v, lam, P) after n_iter iterations from the problem's
+    start, with first-order bounds on the error of an FP32 run: the bound of
+    each iteration's own rounding, evaluated at the oracle's state before
+    it, summed over the iterations (an error carried into the next
+    iteration is taken not to grow; the comparisons check exactly that).
+    Returns (v, lam, P, bounds dict, largest eq. 23 condition number)."""
+    from tests import error_bounds as EB
+    v, lam, P = p.v0, p.lam0, p.P0
+    acc = None
+    kmax = 1.0
+    for _ in range(n_iter):
+        b = EB.as_step_bounds(p.x, v, lam, P, K=K, p_update=p_update, mu=mu)
+        kmax = max(kmax, float(np.max(b["kappa"])))
+        acc = b if acc is None else {k: acc[k] + b[k] for k in ("v", "lam", "P")}
+        if p_update == 0:
+            v, lam, P = oracle.fastfca_as_step(p.x, v, lam, P, K=K)
+        else:
+            v, lam, P = oracle.fastfca_as_step_grad(p.x, v, lam, P, mu, natural=(p_update == 2))
+    return v, lam, P, acc, kmax
+
+
+def check_as_params(got, ref_and_bounds, tol=TOL_PARAM, tag=""):
+    """v, lambda, P of a FastFCA-AS run against oracle_as_bounded's result."""
+    v, lam, P = got
+    v_ref, lam_ref, P_ref, b, _ = ref_and_bounds
+    check("v" + tag, v, v_ref, b["v"], tol)
+    check("lam" + tag, lam, lam_ref, b["lam"], tol)
+    check("P" + tag, P, P_ref, b["P"], tol)
+
+
+def check_loglik_bins(Lb, Lb_ref, tol=TOL_LOGLIK, tag=""):
+    """Per-bin log-likelihoods within tol relative to each bin's value (with
+    a floor of 1e-3 of the mean magnitude for bins whose sum nearly
+    cancels)."""
+    Lb = np.asarray(Lb, np.float64)
+    Lb_ref = np.asarray(Lb_ref, np.float64)
+    scale = np.maximum(np.abs(Lb_ref), 1e-3 * np.mean(np.abs(Lb_ref)))
+    return check("loglik_bins" + tag, Lb, Lb_ref, tol * scale)
 
 
 def oracle_em(p, R, n_iter):

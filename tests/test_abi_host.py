@@ -44,7 +44,7 @@ def lib():
 def test_header_declares_the_expected_calls():
     assert declared_functions() == sorted([
         "fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_separate",
-        "fca_loglik", "fca_loglik_device", "fca_get_params", "fca_set_params", "fca_set_option",
+        "fca_loglik", "fca_loglik_device", "fca_loglik_bins", "fca_get_params", "fca_set_params", "fca_set_option",
         "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
         "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
         "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
@@ -154,3 +154,4 @@ def test_stft_rejects_bad_frames_on_the_host(lib, W, H):
     assert lib.fca_stft(FAKE, 2, 1000, W, H, FAKE, None) == -1
     lib.fca_istft.argtypes = [vp, i, i, i, i, i, i, vp, vp]
     assert lib.fca_istft(FAKE, 2, 2, 3, W, H, 1000, FAKE, None) == -1
+

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 from paper_1805_09498_amd import synth
-from tests.gpu_common import TOL_PARAM, oracle_as, params, problem, rel, run_as, sub_problem, to_dev
+from tests.gpu_common import (TOL_PARAM, check_as_params, oracle_as_bounded, params, problem, rel, run_as,
+                              sub_problem, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,11 +38,8 @@ def test_batch_matches_oracle_per_mixture(ff):
     b, _ = batch_of(ff, probs)
     ff.fca_batch_iterate(b, 1)
     for m, p in enumerate(probs):
-        v, lam, P = params(ff, ff.fca_batch_context(b, m))
-        v_ref, lam_ref, P_ref = oracle_as(p, 1)
-        assert rel(v, v_ref) <= TOL_PARAM, (m, p.shape)
-        assert rel(lam, lam_ref) <= TOL_PARAM, (m, p.shape)
-        assert rel(P, P_ref) <= TOL_PARAM, (m, p.shape)
+        check_as_params(params(ff, ff.fca_batch_context(b, m)), oracle_as_bounded(p, 1),
+                        tag=f" batch mixture {m} {p.shape}")
 
 
 def test_batch_equals_single_contexts_at_the_same_shape(ff):
@@ -108,10 +106,8 @@ def test_full_size_uneven_batch_sampled(ff):
         p = probs[m]
         bins = np.sort(rng.choice(p.shape[0], size=3, replace=False))
         v, lam, P = params(ff, ff.fca_batch_context(b, m))
-        v_ref, lam_ref, P_ref = oracle_as(sub_problem(p, bins), 2)
-        assert rel(v[bins], v_ref) <= TOL_PARAM, (m, p.shape)
-        assert rel(lam[bins], lam_ref) <= TOL_PARAM, (m, p.shape)
-        assert rel(P[bins], P_ref) <= TOL_PARAM, (m, p.shape)
+        check_as_params((v[bins], lam[bins], P[bins]), oracle_as_bounded(sub_problem(p, bins), 2),
+                        tag=f" full batch mixture {m} {p.shape}")
 
 
 def test_batch_options_and_errors(ff):

@@ -1,12 +1,18 @@
 """GPU parity of FastFCA-AS (Section 4.3) against the FP64 oracle, through
-the C ABI, on both execution paths (frequency-resident and streaming)."""
+the C ABI, on both execution paths (frequency-resident and streaming).
+
+Every comparison asserts the per-tensor spec tolerance and, entry by
+entry, the first-order rounding bound of an FP32 run (tests/error_bounds.py,
+computed before the run from the oracle's state; for P it scales with the
+condition number of each eq. 23 matrix)."""
 
 import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, oracle_as, params, problem, rel, run_as,
-                              sub_problem, to_dev)
+from tests import error_bounds as EB
+from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, check, check_as_params, check_loglik_bins,
+                              oracle_as_bounded, params, problem, rel, run_as, sub_problem, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -21,57 +27,80 @@ def ff():
 
 SMALL = dict(I=3, J=3, F=129, N=100, seed=1000)          # small oracle-scale case
 SPEECH = dict(I=3, J=3, F=513, N=626, seed=2000)         # 10 s speech scale
+PAPER = dict(I=3, J=3, F=512, N=249, seed=1500)          # the shape of the paper's experiments
 
 
-@pytest.mark.parametrize("cfg", [SMALL, SPEECH], ids=["small", "speech10s"])
+@pytest.mark.parametrize("cfg", [SMALL, PAPER, SPEECH], ids=["small", "paper", "speech10s"])
 @pytest.mark.parametrize("path", [1, 2], ids=["resident", "streaming"])
 def test_one_iteration_params(ff, cfg, path):
     p = problem(**cfg)
+    ref = oracle_as_bounded(p, 1)
     ctx = run_as(ff, p, 1, path=path)
-    v, lam, P = params(ff, ctx)
-    v_ref, lam_ref, P_ref = oracle_as(p, 1)
-    print(cfg, path, rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref))
-    assert rel(v, v_ref) <= TOL_PARAM
-    assert rel(lam, lam_ref) <= TOL_PARAM
-    assert rel(P, P_ref) <= TOL_PARAM
+    check_as_params(params(ff, ctx), ref, tag=f" {cfg['F']}x{cfg['N']} path {path}")
 
 
-@pytest.mark.parametrize("cfg", [SMALL, SPEECH], ids=["small", "speech10s"])
+@pytest.mark.parametrize("cfg,n_iter", [(SMALL, 10), (PAPER, 20), (SPEECH, 10)], ids=["small", "paper", "speech10s"])
 @pytest.mark.parametrize("path", [1, 2], ids=["resident", "streaming"])
-def test_ten_iterations_loglik(ff, cfg, path):
+def test_loglik_after_iterations(ff, cfg, n_iter, path):
+    """The log-likelihood after the configuration's iterations (10; the
+    paper shape runs its 20), in total and per bin."""
     p = problem(**cfg)
-    ctx = run_as(ff, p, 10, path=path)
+    ctx = run_as(ff, p, n_iter, path=path)
     L = ff.fca_loglik(ctx)
-    v_ref, lam_ref, P_ref = oracle_as(p, 10)
-    L_ref = oracle.loglik_as(p.x, v_ref, lam_ref, P_ref)
+    Lb = ff.fca_loglik_bins(ctx).cpu().numpy()
+    v_ref, lam_ref, P_ref = p.v0, p.lam0, p.P0
+    for _ in range(n_iter):
+        v_ref, lam_ref, P_ref = oracle.fastfca_as_step(p.x, v_ref, lam_ref, P_ref)
+    Lb_ref = oracle.loglik_as(p.x, v_ref, lam_ref, P_ref, per_bin=True)
+    L_ref = float(Lb_ref.sum())
     print(cfg, path, L, L_ref, abs(L - L_ref) / abs(L_ref))
     assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
+    assert abs(Lb.sum() - L) <= 1e-9 * abs(L)
+    check_loglik_bins(Lb, Lb_ref, tag=f" {cfg['F']}x{cfg['N']} {n_iter} iterations path {path}")
+
+
+def test_loglik_headline_run(ff):
+    """The benchmark's job at the 10 s speech shape: 100 iterations, then the
+    log-likelihood, against 100 oracle iterations (total and per bin)."""
+    p = problem(**SPEECH)
+    ctx = run_as(ff, p, 100)
+    L = ff.fca_loglik(ctx)
+    Lb = ff.fca_loglik_bins(ctx).cpu().numpy()
+    v, lam, P = p.v0, p.lam0, p.P0
+    for _ in range(100):
+        v, lam, P = oracle.fastfca_as_step(p.x, v, lam, P)
+    Lb_ref = oracle.loglik_as(p.x, v, lam, P, per_bin=True)
+    L_ref = float(Lb_ref.sum())
+    print("100 iterations", L, L_ref, abs(L - L_ref) / abs(L_ref))
+    assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
+    check_loglik_bins(Lb, Lb_ref, tag=" speech10s 100 iterations")
 
 
 def test_loglik_at_initial_point(ff):
     p = problem(**SMALL)
     ctx = run_as(ff, p, 0)
     L = ff.fca_loglik(ctx)
-    L_ref = oracle.loglik_as(p.x, p.v0, p.lam0, p.P0)
-    assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
+    Lb_ref = oracle.loglik_as(p.x, p.v0, p.lam0, p.P0, per_bin=True)
+    assert abs(L - Lb_ref.sum()) <= TOL_LOGLIK * abs(Lb_ref.sum())
+    # at the initial point the only error is the evaluation's own rounding
+    bound = EB.loglik_bin_bounds(p.x, p.v0, p.lam0, p.P0)
+    check("loglik_bins initial point", ff.fca_loglik_bins(ctx).cpu().numpy(), Lb_ref, bound)
 
 
 @pytest.mark.parametrize("waves,bpw", [(1, 1), (2, 1), (4, 1), (2, 2), (4, 2)])
 def test_resident_launch_shapes_agree(ff, waves, bpw):
     p = problem(**SPEECH)          # F = 513: the last workgroup of a 2-bin shape holds one bin
+    ref = oracle_as_bounded(p, 1)
     ctx = run_as(ff, p, 1, path=1, waves=waves, bpw=bpw)
-    v, lam, P = params(ff, ctx)
-    v_ref, lam_ref, P_ref = oracle_as(p, 1)
-    assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM
+    check_as_params(params(ff, ctx), ref, tag=f" w{waves}b{bpw}")
 
 
 def test_inner_fixed_point_steps(ff):
     p = problem(3, 3, 33, 90, seed=5)
+    ref = oracle_as_bounded(p, 1, K=3)
     for path in (1, 2):
         ctx = run_as(ff, p, 1, path=path, K=3)
-        v, lam, P = params(ff, ctx)
-        v_ref, lam_ref, P_ref = oracle_as(p, 1, K=3)
-        assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM
+        check_as_params(params(ff, ctx), ref, tag=f" K3 path {path}")
 
 
 @pytest.mark.parametrize("I,J", [(4, 3), (6, 4)])
@@ -79,11 +108,10 @@ def test_inner_fixed_point_steps_larger_I(ff, I, J):
     """K = 3 at I = 4 (resident and streaming kernels) and I = 6 (streaming
     only: the automatic path picks it, forcing the resident one is refused)."""
     p = problem(I, J, 9, 70, seed=6)
-    v_ref, lam_ref, P_ref = oracle_as(p, 1, K=3)
+    ref = oracle_as_bounded(p, 1, K=3)
     for path in ((0, 1, 2) if I <= 4 else (0, 2)):
         ctx = run_as(ff, p, 1, path=path, K=3)
-        v, lam, P = params(ff, ctx)
-        assert max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref)) <= TOL_PARAM, path
+        check_as_params(params(ff, ctx), ref, tag=f" K3 I{I} path {path}")
     if I > 4:
         with pytest.raises(ff.FcaError):
             run_as(ff, p, 1, path=1, K=3)
@@ -93,22 +121,19 @@ def test_inner_fixed_point_steps_larger_I(ff, I, J):
 def test_ill_conditioned_low_bins_over_iterations(ff, I, J, N):
     """Plane waves in a diffuse field on a uniform array: near DC the weighted
     covariances of eq. 23 reach condition numbers of 1e3 - 1e4.  Parameters
-    after 1, 2 and 3 iterations against the oracle, every bin.  The bound is
-    TOL_PARAM after the first iteration and grows linearly with the count:
-    each iteration starts from the previous one's single-precision state, and
-    the rounding of eq. 23's sums reaches P through these condition numbers
-    (measured on this case: ~3e-5 after one iteration, 5e-5 - 1e-4 after
-    three, varying by 2x between builds whose sums round differently)."""
+    after 1, 2 and 3 iterations against the oracle, every entry of every
+    bin, within the sum of the iterations' first-order rounding bounds
+    (each computed from the condition numbers at the oracle's state before
+    that iteration; printed)."""
     p = problem(I, J, 9, N, seed=17, spatial="ula")
     ctx = run_as(ff, p, 0)
-    v_ref, lam_ref, P_ref = p.v0, p.lam0, p.P0
     for it in range(3):
         ff.fastfca_as_iterate(ctx, 1)
-        v_ref, lam_ref, P_ref = oracle.fastfca_as_step(p.x, v_ref, lam_ref, P_ref)
-        v, lam, P = params(ff, ctx)
-        err = max(rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref))
-        print("iteration", it + 1, "error %.2e" % err)
-        assert err <= TOL_PARAM * (it + 1), it
+        ref = oracle_as_bounded(p, it + 1)
+        print("iteration", it + 1, "largest eq. 23 condition number %.3g" % ref[4])
+        # the north-star tolerance is stated for one iteration; later ones
+        # carry the derived bounds only
+        check_as_params(params(ff, ctx), ref, tol=TOL_PARAM if it == 0 else None, tag=f" ula I{I} it {it + 1}")
 
 
 def test_wiener_sums_to_mixture_and_matches_oracle(ff):
@@ -118,7 +143,7 @@ def test_wiener_sums_to_mixture_and_matches_oracle(ff):
     s = ff.fca_wiener_separate(ctx).cpu().numpy().astype(np.complex128)
     assert rel(s.sum(axis=0), p.x) <= 1e-5
     s_ref = oracle.wiener_as(p.x, v, lam, P)   # oracle on the GPU's own parameters
-    assert rel(s, s_ref) <= TOL_PARAM
+    check("wiener", s, s_ref, EB.as_wiener_bounds(p.x, v, lam, P), TOL_PARAM, axis=1)
 
 
 def test_resume_is_bitwise(ff):
@@ -145,15 +170,16 @@ def test_deterministic(ff):
         np.testing.assert_array_equal(a, b)
 
 
-def test_full_size_long_array_sampled_bins(ff):
-    """I=8, J=6, F=1025, N=3750 (60 s, plane-wave + diffuse covariances,
-    sparse log-normal spectra): one iteration on the whole problem, compared
-    on sampled bins with the oracle run on those bins alone."""
-    p = problem(8, 6, 1025, 3750, seed=3001, spatial="ula", psd="lognormal")
+@pytest.mark.parametrize("I,J,seed,bins", [(8, 6, 3001, [0, 1, 137, 512, 800, 1024]),
+                                           (6, 4, 3000, [0, 2, 250, 700, 1024])], ids=["long8x6", "long6x4"])
+def test_full_size_long_array_sampled_bins(ff, I, J, seed, bins):
+    """The 60 s workloads (F=1025, N=3750, plane-wave + diffuse covariances,
+    sparse log-normal spectra): one iteration on the whole problem in the
+    launch configuration the benchmark uses, compared bin by bin on sampled
+    bins with the oracle run on those bins alone."""
+    p = problem(I, J, 1025, 3750, seed=seed, spatial="ula", psd="lognormal")
     ctx = run_as(ff, p, 1)
     v, lam, P = params(ff, ctx)
-    bins = np.array([0, 1, 137, 512, 800, 1024])
-    v_ref, lam_ref, P_ref = oracle_as(sub_problem(p, bins), 1)
-    assert rel(v[bins], v_ref) <= TOL_PARAM
-    assert rel(lam[bins], lam_ref) <= TOL_PARAM
-    assert rel(P[bins], P_ref) <= TOL_PARAM
+    bins = np.array(bins)
+    ref = oracle_as_bounded(sub_problem(p, bins), 1)
+    check_as_params((v[bins], lam[bins], P[bins]), ref, tag=f" long{I}x{J} sampled")

@@ -7,7 +7,10 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_common import TOL_LOGLIK, TOL_PARAM, oracle_as, oracle_em, params, problem, rel, run_as, to_dev
+from tests import error_bounds as EB
+from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, check, check_as_params, check_loglik_bins, oracle_as,
+                              oracle_as_bounded, oracle_em, params, problem, rel, run_as, to_dev)
+from tests.test_parity_em import em_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -31,27 +34,26 @@ CASES = [
 @pytest.mark.parametrize("I,J,F,N", CASES)
 def test_as_edge_shapes(ff, I, J, F, N):
     p = problem(I, J, F, N, seed=100 * I + 10 * J + F)
-    v_ref, lam_ref, P_ref = oracle_as(p, 1)
+    ref = oracle_as_bounded(p, 1)
     for path in (0, 2):
         ctx = run_as(ff, p, 1, path=path)
-        v, lam, P = params(ff, ctx)
-        assert rel(v, v_ref) <= TOL_PARAM, (path, rel(v, v_ref))
-        assert rel(lam, lam_ref) <= TOL_PARAM, (path, rel(lam, lam_ref))
-        assert rel(P, P_ref) <= TOL_PARAM, (path, rel(P, P_ref))
+        check_as_params(params(ff, ctx), ref, tag=f" edge I{I} J{J} F{F} N{N} path {path}")
 
 
 @pytest.mark.parametrize("I,J,F,N", CASES)
 def test_em_edge_shapes(ff, I, J, F, N):
     p = problem(I, J, F, N, seed=100 * I + 10 * J + F)
-    v_ref, R_ref = oracle_em(p, oracle.as_spatial_cov(p.P0, p.lam0), 1)
+    S0 = oracle.as_spatial_cov(p.P0, p.lam0)
+    v_ref, R_ref = oracle_em(p, S0, 1)
+    b = em_bounds(p.x, p.v0, S0)
     for path in (0, 2):
         t = to_dev(p)
         ctx = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"])
         ff.fca_set_option(ctx, "path", path)
         ff.fca_em_iterate(ctx, 1)
         v, _, R = params(ff, ctx)
-        assert rel(v, v_ref) <= TOL_PARAM, (path, rel(v, v_ref))
-        assert rel(R, R_ref) <= TOL_PARAM, (path, rel(R, R_ref))
+        check(f"em v edge I{I} J{J} F{F} N{N} path {path}", v, v_ref, b["v"], TOL_PARAM)
+        check(f"em S edge I{I} J{J} F{F} N{N} path {path}", R, R_ref, b["S"], TOL_PARAM)
 
 
 @pytest.mark.parametrize("I,J,F,N", [(1, 2, 4, 7), (2, 3, 7, 65), (8, 9, 2, 700), (6, 7, 3, 2049)])
@@ -61,9 +63,13 @@ def test_loglik_and_wiener_edge(ff, I, J, F, N):
     v, lam, P = params(ff, ctx)
     L = ff.fca_loglik(ctx)
     assert abs(L - oracle.loglik_as(p.x, v, lam, P)) <= TOL_LOGLIK * abs(L)
+    # on the GPU's own parameters the only error is the evaluation's rounding
+    check(f"loglik_bins edge I{I} J{J}", ff.fca_loglik_bins(ctx).cpu().numpy(),
+          oracle.loglik_as(p.x, v, lam, P, per_bin=True), EB.loglik_bin_bounds(p.x, v, lam, P))
     s = ff.fca_wiener_separate(ctx).cpu().numpy().astype(np.complex128)
     assert rel(s.sum(axis=0), p.x) <= 1e-5
-    assert rel(s, oracle.wiener_as(p.x, v, lam, P)) <= TOL_PARAM
+    check(f"wiener edge I{I} J{J}", s, oracle.wiener_as(p.x, v, lam, P), EB.as_wiener_bounds(p.x, v, lam, P),
+          TOL_PARAM, axis=1)
 
 
 @pytest.mark.parametrize("method", ["as", "em"])
@@ -98,7 +104,7 @@ def test_split_streams_same_bits(ff, I, J, F, N):
     multiple of the parts, fewer bins than parts, F = 1), and match the oracle
     after one iteration."""
     p = problem(I, J, F, N, seed=500 + 10 * I + F)
-    v_ref, lam_ref, P_ref = oracle_as(p, 1)
+    ref = oracle_as_bounded(p, 1)
     runs = []
     for split in (1, 2, 3, 4):
         t = to_dev(p)
@@ -107,8 +113,7 @@ def test_split_streams_same_bits(ff, I, J, F, N):
         ff.fca_set_option(ctx, "split_streams", split)
         assert ff.fca_get_option(ctx, "split_streams") == split
         ff.fastfca_as_iterate(ctx, 1)
-        v, lam, P = params(ff, ctx)
-        assert rel(v, v_ref) <= TOL_PARAM and rel(lam, lam_ref) <= TOL_PARAM and rel(P, P_ref) <= TOL_PARAM
+        check_as_params(params(ff, ctx), ref, tag=f" split {split} I{I}")
         ff.fastfca_as_iterate(ctx, 4)
         runs.append(params(ff, ctx))
     for other in runs[1:]:

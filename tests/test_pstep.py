@@ -1,14 +1,15 @@
 """GPU parity of the gradient-type P updates (option "p_update": 1 gradient,
 2 natural gradient; real option "p_step") against the oracle
 (oracle.fastfca_as_step_grad), on both execution paths, after 1 and 3
-iterations, at the parameter tolerance of the fixed-point update."""
+iterations, at the parameter tolerance of the fixed-point update and entry
+by entry within the summed first-order rounding bounds of the iterations."""
 
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from tests.gpu_common import TOL_PARAM, params, problem, rel, to_dev
+from tests.gpu_common import TOL_PARAM, check_as_params, oracle_as_bounded, params, problem, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -36,14 +37,10 @@ def test_gradient_type_steps_match_oracle(ff, p_update, mu, I, J):
     p = problem(I, J, 9, 150, seed=70 + I)
     paths = (0, 2) if (p_update == 1 and I > 4) else (0, 1, 2)
     for n_iter in (1, 3):
-        v_ref, lam_ref, P_ref = p.v0, p.lam0, p.P0
-        for _ in range(n_iter):
-            v_ref, lam_ref, P_ref = oracle.fastfca_as_step_grad(p.x, v_ref, lam_ref, P_ref, mu, natural=(p_update == 2))
+        ref = oracle_as_bounded(p, n_iter, p_update=p_update, mu=mu)
         for path in paths:
             ctx = run(ff, p, n_iter, p_update, mu, path)
-            v, lam, P = params(ff, ctx)
-            err = (rel(v, v_ref), rel(lam, lam_ref), rel(P, P_ref))
-            assert max(err) <= TOL_PARAM, (n_iter, path, err)
+            check_as_params(params(ff, ctx), ref, tag=f" p_update {p_update} I{I} J{J} it {n_iter} path {path}")
     if p_update == 1 and I > 4:
         with pytest.raises(ff.FcaError):
             run(ff, p, 1, p_update, mu, 1)             # the resident kernels take it up to I = 4

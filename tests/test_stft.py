@@ -5,7 +5,13 @@ separation (STFT, FastFCA-AS iterations, Wiener filter, overlap-add).
 Tolerance: relative Frobenius error <= 1e-5 for the transforms (a radix-2
 FP32 FFT of length W loses ~log2(W) * 6e-8 relative; W <= 2048 gives
 <= 7e-7) and <= 1e-4 after the separation, the parameter tolerance of the
-iterations."""
+iterations.  Entry by entry: a radix-2 FFT of length W has a norm-wise
+relative error of at most log2(W) (gamma(4) (sqrt 2 + mu) + mu), mu the
+twiddles' error (Higham, ch. 24); per frame that bounds every bin of the
+analysis by gamma(8 log2 W + 8) sqrt(2) |X_frame| (Parseval over the half
+spectrum), and every synthesised sample by
+2 gamma(8 log2 W + 12) sqrt(2 / W) max_frame |S_frame| (W / hop frames
+overlap, each scaled by 2 hop / W)."""
 
 import numpy as np
 import pytest
@@ -14,7 +20,8 @@ import torch
 import oracle
 from oracle import stft as S
 from paper_1805_09498_amd import synth
-from tests.gpu_common import rel
+from tests import error_bounds as EB
+from tests.gpu_common import check, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +45,8 @@ def test_stft_matches_oracle(ff, C, L, W, H):
     torch.cuda.synchronize()
     ref = S.stft(wav, W, H)
     assert X.shape == ref.shape
-    assert rel(X.cpu().numpy(), ref) <= 1e-5
+    bound = EB.gamma(8 * int(np.log2(W)) + 8) * np.sqrt(2.0) * np.linalg.norm(ref, axis=0, keepdims=True)
+    check(f"stft C{C} L{L} W{W} H{H}", X.cpu().numpy(), ref, bound, 1e-5)
 
 
 @pytest.mark.parametrize("J,C,L,W,H", [(3, 3, 16000, 1024, 512), (2, 2, 9000, 2048, 256), (1, 1, 100, 16, 4)])
@@ -49,7 +57,9 @@ def test_istft_matches_oracle(ff, J, C, L, W, H):
     out = ff.fca_istft(torch.from_numpy(spec).cuda(), L, W, H)
     torch.cuda.synchronize()
     ref = np.stack([S.istft(spec[j].astype(np.complex128), W, H, L) for j in range(J)])
-    assert rel(out.cpu().numpy(), ref) <= 1e-5
+    smax = np.linalg.norm(spec.astype(np.complex128), axis=1).max(axis=1)          # [J][C]
+    bound = 2.0 * EB.gamma(8 * int(np.log2(W)) + 12) * np.sqrt(2.0 / W) * smax[:, :, None]
+    check(f"istft J{J} C{C} L{L} W{W} H{H}", out.cpu().numpy(), ref, bound, 1e-5)
 
 
 @pytest.mark.parametrize("W,H", [(1024, 512), (2048, 256)])
