@@ -67,7 +67,7 @@ def fca_em_flops_per_point_iter(I, J):
 
 # What each profiled kernel compiles from (the counters are void once these change).
 RESIDENT_SOURCES = ("fca_resident.h", "fca_point.h", "fca_device.h", "fca_state.h")
-STREAM_SOURCES = ("fca_kernels.h", "fca_point.h", "fca_device.h", "fca_state.h")
+STREAM_SOURCES = ("fca_kernels.h", "fca_pvariants.h", "fca_point.h", "fca_device.h", "fca_state.h")
 
 
 def _sources_hash(files):
@@ -344,7 +344,7 @@ def workload_leg(ff, name, steps, warmup, em_steps):
     return leg
 
 
-def batch_leg(ff, steps, warmup, iters=30, graph=1):
+def batch_leg(ff, steps, warmup, iters=30, graph=1, queues=(0, 1)):
     """Uneven batch: 64 mixtures (N ~ U[200, 2000], I in {2,3,4,6},
     J ~ U[2, I+1], F = 513), `iters` FastFCA-AS iterations per step through
     the batch API (one launch per (I, J) group, replayed as a HIP graph)."""
@@ -373,20 +373,28 @@ def batch_leg(ff, steps, warmup, iters=30, graph=1):
         e1.record(stream)
         return e0, e1
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ev.append(step())
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    it_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
+    def timed():
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ev.append(step())
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, float(np.mean([a.elapsed_time(c) for a, c in ev]))
+
+    # one workgroup per (mixture, bin) tile (the default), then the
+    # persistent work-queue form of the same launches
+    per_queue = {}
+    for q in queues:
+        ff.fca_batch_set_option(b, "queue", q)
+        per_queue[q] = timed()
+    ms, it_ms = per_queue[queues[0]]
     pts = sum(s[0] * s[1] for s in shapes) * iters
     groups = []
     for g in range(ff.fca_batch_get_option(b, "groups")):
-        groups.append({k: ff.fca_batch_get_option(b, "group_" + k, g) for k in ("I", "J", "tiles", "waves")})
+        groups.append({k: ff.fca_batch_get_option(b, "group_" + k, g) for k in ("I", "J", "tiles", "waves", "queued")})
     flops = sum(as_flops_per_point_iter(s[2], s[3]) * s[0] * s[1] for s in shapes) * iters
     bytes_alg = sum(as_bytes_per_point_iter(s[2], s[3]) * s[0] * s[1] for s in shapes) * iters
     tflops = flops / (it_ms * 1e-3) / 1e12
@@ -399,6 +407,10 @@ def batch_leg(ff, steps, warmup, iters=30, graph=1):
                          "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                          "algorithmic_GBps": bytes_alg / (it_ms * 1e-3) / 1e9,
                          "kernel": "k_as_resident_batch, one launch per (I, J) group"},
+            "work_queue": {"value": pts / (per_queue[1][0] * 1e-3), "ms_per_step": per_queue[1][0],
+                           "iterate_ms": per_queue[1][1],
+                           "kernel": "k_as_resident_batch_q: persistent workgroups, device tile counter"}
+            if 1 in per_queue and queues[0] != 1 else None,
             "groups": groups}
 
 

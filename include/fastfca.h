@@ -62,9 +62,12 @@ typedef enum {
   FCA_ERR_UNSUPPORTED = -2, /* (I, J) outside the instantiated range */
   FCA_ERR_HIP = -3,         /* a HIP runtime call failed; see fca_last_error */
   FCA_ERR_STATE = -4,       /* call does not match the context's method */
-  FCA_ERR_NONFINITE = -5    /* non-finite parameters found (check_finite=1);
-                               this is also how a singular P(f) or weighted
-                               covariance shows up */
+  FCA_ERR_NONFINITE = -5,   /* non-finite parameters after an update
+                               (check_finite=1) */
+  FCA_ERR_SINGULAR = -6     /* check_finite=1: P(f) singular or S_j(f) not
+                               positive definite in the given parameters, or
+                               a pivot <= 0 in an update's solves (a weighted
+                               covariance of eq. 23, or C / S_j of FCA EM) */
 } fca_status;
 
 typedef enum {
@@ -136,14 +139,29 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
                           const fca_c64 *P_or_R);
 
 /* Options: "K" (fixed-point steps per hybrid iteration, 1..64, default 1),
- * "p_update" (FastFCA-AS only; how step 2 of a hybrid iteration updates P:
+ * "p_update" (FastFCA-AS only; how step 2 of a hybrid iteration updates P --
+ * the fixed-point update and the alternatives named in Section 4.5:
  * 0 = the fixed-point update of eq. 23 (default), 1 = gradient ascent
  * P + mu g, 2 = natural (relative) gradient P + mu P P^H g, with
  * g = (1/N) dL2/dP* of eq. 21 at the new v, lambda and mu the real option
- * "p_step" (default 0.1) -- the alternatives named in Section 4.5; K applies
- * to the fixed-point update only),
- * "check_finite" (0/1: after each iterate call, synchronise and return
- * FCA_ERR_NONFINITE if a parameter is NaN/Inf), "path" (0 = automatic,
+ * "p_step" (default 0.1), 3 = one Newton step on L2 (eq. 14) in P with
+ * v, lambda held (the columns' phases, which L2 ignores, unchanged to first
+ * order), 4 = EM with P in the M-step: after the E-step at the current
+ * parameters, eq. 19-20 and then one sweep of column-wise maximisations of
+ * the Q-function (eq. 18) over P, p_i <- V_i^-1 [P^-H]_i scaled to
+ * p_i^H V_i p_i = 1; K applies to the fixed-point update only; 3 and 4 run
+ * on the streaming kernels),
+ * "check_finite" (0/1, default 0.  With 1, iterate calls synchronise and
+ * check on the device: (a) once after fca_init or fca_set_params, before
+ * iterating, the parameters the model requires (Section 3.1, eq. 12):
+ * v(n,f) > 0 and finite for every frame, lambda > 0 and finite, P(f)
+ * non-singular to single precision (an LU pivot's modulus above
+ * I 2^-23 times the largest entry's), or for EM every S_j(f) positive
+ * definite -- FCA_ERR_ARG for v / lambda, FCA_ERR_SINGULAR for P / S, and
+ * nothing is iterated; (b) after the iterations, FCA_ERR_SINGULAR if a
+ * solve met a pivot <= 0 (a weighted covariance of eq. 23, or C / S_j of
+ * FCA EM; e.g. a bin whose mixture is zero), else FCA_ERR_NONFINITE if a
+ * parameter is NaN/Inf), "path" (0 = automatic,
  * 1 = force the frequency-resident kernels, 2 = force the streaming
  * kernels; K > 1 or the gradient P step at I > 4 always use the streaming
  * kernels), "waves"
@@ -217,14 +235,20 @@ fca_status fca_batch_iterate(fca_batch *b, int n_iter);
 fca_status fca_batch_context(fca_batch *b, int m, fca_ctx **ctx);
 
 /* "graph" (1 = default: replay a recorded HIP graph per batch step; 0 =
- * launch directly), "autotune" (1 = default, 0 = smallest fitting shape),
+ * launch directly), "queue" (0 = default: one workgroup per (mixture, bin)
+ * tile in the table's order; 1 = a persistent grid of as many workgroups as
+ * fit on the device that take tiles from a device counter, for the groups
+ * whose queue kernel needs no scratch memory, the first form for the others;
+ * the results are bitwise the same), "autotune" (1 = default, 0 = smallest fitting shape),
  * "waves" (0 = automatic, 1, 2 or 4), "K" (fixed-point steps, 1..64, applied
  * to every mixture). */
 fca_status fca_batch_set_option(fca_batch *b, const char *key, long long value);
 
 /* "groups" (number of (I, J) groups; group ignored), per group index:
  * "group_I", "group_J", "group_tiles", "group_waves" (waves per workgroup
- * chosen, 0 = streaming kernels, -1 = not tuned yet).  value: host pointer. */
+ * chosen, 0 = streaming kernels, -1 = not tuned yet), "group_queued" (1 if
+ * the group's last launch took the work-queue form); "queue" (group
+ * ignored).  value: host pointer. */
 fca_status fca_batch_get_option(fca_batch *b, const char *key, int group, long long *value);
 
 /* Message for the last error on b, or for the calling thread's last failed

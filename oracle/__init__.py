@@ -44,6 +44,11 @@ from .fastfca_as import (
     as_fpi_dense_vec,
     as_gradient_p_step,
     fastfca_as_step_grad,
+    as_newton_p_step,
+    as_newton_system,
+    newton_directions,
+    fastfca_as_step_newton,
+    as_em_p_step,
 )
 
 __all__ = [
@@ -51,4 +56,5 @@ __all__ = [
     "wiener_fca", "as_spatial_cov", "as_estep", "as_em_half_step",
     "as_fpi_step", "fastfca_as_step", "loglik_as", "wiener_as",
     "as_wirtinger_grad", "as_fpi_dense_vec", "as_gradient_p_step", "fastfca_as_step_grad",
+    "as_newton_p_step", "as_newton_system", "newton_directions", "fastfca_as_step_newton", "as_em_p_step",
 ]

@@ -131,6 +131,115 @@ def fastfca_as_step_grad(x, v, lam, P, mu, natural=False):
     return v_new, lam_new, as_gradient_p_step(x, v_new, lam_new, P, mu, natural)
 
 
+def as_newton_p_step(x, v, lam, P):
+    """Newton's method in place of the fixed-point P update (an alternative
+    Section 4.5 names): one full Newton step on L2 (eq. 14) as a function of
+    P(f) alone, v and Lambda held, no damping or line search.
+
+    Per bin, with Q_i the matrices of eq. 23, L2 / N equals, up to terms free
+    of P,  f(P) = 2 ln|det P| - sum_i p_i^H Q_i p_i.  Its derivatives along
+    complex directions E, F (I x I) are
+      df[E]      = 2 Re tr(G^H E),   G = P^-H - [Q_1 p_1, ..., Q_I p_I]
+                                        = (1/N) dL2/dP*  (eq. 21),
+      d2f[E, F]  = -2 Re tr(P^-1 E P^-1 F) - 2 sum_i Re(E_i^H Q_i F_i).
+    f does not change when a column of P is multiplied by a unit complex
+    number, so the Hessian is singular along E = P i D (D real diagonal).
+    The step is taken in the relative form P + P X (the form of the other P
+    updates) over the real directions U of X other than the imaginary
+    diagonal entries (the columns' phases are left alone to first order):
+    with E_k = P U_k the reduced Hessian H_kl = d2f[E_k, E_l] and gradient
+    g_k = df[E_k] are formed entry by entry, H s = -g is solved densely and
+    P + P sum_k s_k U_k is returned.
+    """
+    P = np.asarray(P, dtype=np.complex128)
+    basis = newton_directions(P.shape[1])
+    out = np.empty_like(P)
+    for f, (H, grad) in enumerate(as_newton_system(x, v, lam, P)):
+        step = np.linalg.solve(H, -grad)
+        X = sum(w * U for w, U in zip(step, basis))
+        out[f] = P[f] + P[f] @ X
+    return out
+
+
+def as_newton_system(x, v, lam, P):
+    """The reduced Hessian and gradient of Newton's P step (see
+    as_newton_p_step), one (H, g) pair per bin, over the directions
+    P U_k with U_k from newton_directions."""
+    x = np.asarray(x, dtype=np.complex128)
+    P = np.asarray(P, dtype=np.complex128)
+    F, I = P.shape[0], P.shape[1]
+    Q = as_weighted_covs(x, v, lam)                      # [F][i][I][I]
+    basis = newton_directions(I)
+    systems = []
+    for f in range(F):
+        Pinv = np.linalg.inv(P[f])
+        G = _herm(Pinv) - np.stack([Q[f, i] @ P[f, :, i] for i in range(I)], axis=1)
+        dirs = [P[f] @ U for U in basis]
+        grad = np.array([2.0 * np.real(np.trace(_herm(G) @ E)) for E in dirs])
+        H = np.empty((len(dirs), len(dirs)))
+        for k, E in enumerate(dirs):
+            for l, Fd in enumerate(dirs):
+                quad = sum(np.real(np.conj(E[:, i]) @ Q[f, i] @ Fd[:, i]) for i in range(I))
+                H[k, l] = -2.0 * np.real(np.trace(Pinv @ E @ Pinv @ Fd)) - 2.0 * quad
+        systems.append((H, grad))
+    return systems
+
+
+def newton_directions(I):
+    """The real directions of X in Newton's P step: a unit real entry at
+    every (a, c), a unit imaginary entry at every (a, c) with a != c."""
+    basis = []
+    for part in (1.0, 1j):
+        for a in range(I):
+            for c in range(I):
+                if part == 1j and a == c:
+                    continue
+                U = np.zeros((I, I), dtype=np.complex128)
+                U[a, c] = part
+                basis.append(U)
+    return basis
+
+
+def as_em_p_step(x, v, lam, P, sweeps=1):
+    """The normal EM algorithm with P in the M-step (named in Section 4.5):
+    the E-step at (v, Lambda, P) gives the posterior moments of every source
+    image in the basis of x (eq. 7-8 with the covariances of eq. 12); the
+    M-step raises the Q-function (eq. 18) over v and Lambda (eq. 19-20 with
+    the current P) and then over P with the new v, Lambda.
+
+    As a function of P, Q is  2NJ ln|det P| - NJ sum_i p_i^H V_i p_i + const
+    with V_i = (1/(NJ)) sum_{n,j} (mu_j mu_j^H + Phi_j) / (v_j lambda_ji)
+    (new v, Lambda).  The column update p_i <- V_i^-1 [P^-H]_i rescaled to
+    p_i^H V_i p_i = 1 maximises Q over p_i with the other columns held
+    (iterative projection); `sweeps` passes over i = 1..I, each column using
+    the P that the previous columns left.  Every step raises Q, so the
+    iteration is a generalised EM algorithm.  Returns (v, Lambda, P).
+    """
+    from .fca import fca_estep
+    x = np.asarray(x, dtype=np.complex128)
+    P = np.asarray(P, dtype=np.complex128).copy()
+    F, N, I = x.shape
+    mu, Phi = fca_estep(x, np.asarray(v, np.float64), as_spatial_cov(P, lam))
+    v_new, lam_new = as_em_half_step(x, v, lam, P)
+    J = v_new.shape[2]
+    M = np.einsum("fnja,fnjb->fnjab", mu, np.conj(mu)) + Phi
+    V = np.einsum("fnjab,fnj,fji->fiab", M, 1.0 / v_new, 1.0 / lam_new) / (N * J)
+    for _ in range(sweeps):
+        for i in range(I):
+            b = _herm(np.linalg.inv(P))[:, :, i]
+            p = np.linalg.solve(V[:, i], b[..., None])[..., 0]
+            scale = np.sqrt(np.real(np.einsum("fa,fab,fb->f", np.conj(p), V[:, i], p)))
+            P[:, :, i] = p / scale[:, None]
+    return v_new, lam_new, P
+
+
+def fastfca_as_step_newton(x, v, lam, P):
+    """A hybrid iteration with Newton's P update: the EM step on (Lambda, v),
+    then as_newton_p_step with the new (v, Lambda)."""
+    v_new, lam_new = as_em_half_step(x, v, lam, P)
+    return v_new, lam_new, as_newton_p_step(x, v_new, lam_new, P)
+
+
 def fastfca_as_step(x, v, lam, P, K=1):
     """One hybrid iteration of FastFCA-AS (Section 4.3): EM on (Lambda, v),
     then the fixed-point update of P with the new (Lambda, v).

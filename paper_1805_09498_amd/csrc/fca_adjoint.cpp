@@ -120,6 +120,10 @@ fca_status fastfca_as_forward(fca_ctx* c, int n_iter, int ckpt_every, fca_c64* o
     c->tape_bytes = bytes;
   }
   c->tape_version = ~0ULL;
+  {
+    fca_status pst = fca::pre_iterate(c);
+    if (pst != FCA_OK) return pst;
+  }
   int waves = 0, bpw = 0;
   bool last_rec = false;
   for (int k = 0; k < t.n_ck; ++k) {

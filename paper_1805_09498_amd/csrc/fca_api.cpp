@@ -88,6 +88,7 @@ std::map<std::tuple<int, int, int, int, int, int, int>, Shape> g_tuned;  // (met
 bool shape_fits(const fca_ctx* c, Shape sh) {
   if (sh.waves == 0) return true;
   if (c->method == FCA_METHOD_AS && (c->s.K > 1 || c->s.p_update == 1) && c->I > fca::kResMaxIK) return false;
+  if (c->method == FCA_METHOD_AS && c->s.p_update >= 3) return false;  // Newton / EM with P: streaming kernels
   return c->method == FCA_METHOD_AS ? c->ks->as_resident_fits(c->N, sh.waves, sh.bpw) != 0
                                     : (sh.bpw == 1 && c->ks->em_resident_fits(c->N, sh.waves) != 0);
 }
@@ -103,8 +104,9 @@ DevState bin_view(const fca_ctx* c, int f0, int nf) {
   v.vs = s.vs + f * J * Np;
   v.lam = s.lam + f * J * I;
   v.P = s.P + f * I * I;
-  v.partA = s.partA + f * s.nchunk * J * I;
+  v.partA = s.partA + f * s.nchunk * J * (I + 1);
   v.partB = s.partB + f * s.nchunk * I * I * I;
+  v.partE = s.partE + f * s.nchunk * J * (I * I + I);
   v.partL = s.partL + f * (s.nchunk > s.nchunk_em ? s.nchunk : s.nchunk_em);
   v.llf = s.llf + f;
   return v;
@@ -220,7 +222,9 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
   if (c->path == 1) {
     bool any = false;
     for (int k = 0; k < ncand; ++k) any = any || (cands[k].waves > 0 && shape_fits(c, cands[k]));
-    if (!any) return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this problem (N, or K > 1 / gradient P step at I > 4)");
+    if (!any)
+      return fail(c, FCA_ERR_ARG, "the frequency-resident path does not fit this problem (N, K > 1 or the gradient "
+                                  "P step at I > 4, or Newton's / the EM P update, which use the streaming kernels)");
   }
   const bool forced = c->waves > 0 || c->bpw > 0;
   if (forced || !c->autotune) {
@@ -308,12 +312,41 @@ fca_status choose_shape(fca_ctx* c, int n_iter_hint, Shape* out) {
   return FCA_OK;
 }
 
+// The device flag after the work queued so far (synchronises the stream).
+fca_status read_flag(fca_ctx* c, int* h) {
+  hipError_t e = hipMemcpyAsync(h, c->s.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  return FCA_OK;
+}
+
+fca_status pre_check(fca_ctx* c) {
+  if (!c->check_finite) return FCA_OK;
+  const DevState& s = c->s;
+  const bool as = c->method == FCA_METHOD_AS;
+  hipError_t e = fca::launch_set_flag(s.flag, 0, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "flag reset");
+  if (c->params_checked) return FCA_OK;
+  e = fca::launch_check_positive(s.vs, c->F, c->J, c->N, s.Npad, as ? s.lam : nullptr,
+                                 as ? (long long)c->F * c->J * c->I : 0, s.flag, c->stream);
+  if (e == hipSuccess) e = c->ks->check_matrices(s, c->stream, as ? 0 : 1);
+  if (e != hipSuccess) return hip_fail(c, e, "parameter check");
+  int h = 0;
+  fca_status st = read_flag(c, &h);
+  if (st != FCA_OK) return st;
+  if (h & fca::kFlagNonPositive) return fail(c, FCA_ERR_ARG, as ? "v or lambda is not positive and finite" : "v is not positive and finite");
+  if (h & fca::kFlagSingularParam)
+    return fail(c, FCA_ERR_SINGULAR, as ? "P(f) is singular (to single precision) in some bin"
+                                        : "S_j(f) is not positive definite in some bin");
+  c->params_checked = 1;
+  return FCA_OK;
+}
+
 fca_status post_check(fca_ctx* c) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   if (!c->check_finite) return FCA_OK;
   const DevState& s = c->s;
-  if ((e = hipMemsetAsync(s.flag, 0, sizeof(int), c->stream)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
   e = fca::launch_check_finite(s.vs, (long long)c->F * c->J * s.Npad, s.flag, c->stream);
   if (e == hipSuccess && c->method == FCA_METHOD_AS) {
     e = fca::launch_check_finite(s.lam, (long long)c->F * c->J * c->I, s.flag, c->stream);
@@ -324,9 +357,12 @@ fca_status post_check(fca_ctx* c) {
   }
   if (e != hipSuccess) return hip_fail(c, e, "finiteness check");
   int h = 0;
-  if ((e = hipMemcpyAsync(&h, s.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
-    return hip_fail(c, e, "hipMemcpyAsync");
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  fca_status st = read_flag(c, &h);
+  if (st != FCA_OK) return st;
+  if (h & fca::kFlagSingular)
+    return fail(c, FCA_ERR_SINGULAR, c->method == FCA_METHOD_AS
+                                         ? "a weighted covariance of eq. 23 is not positive definite (pivot <= 0)"
+                                         : "a model covariance C or an S_j is not positive definite (pivot <= 0)");
   if (h) return fail(c, FCA_ERR_NONFINITE, "non-finite parameter values after the update");
   return FCA_OK;
 }
@@ -382,6 +418,7 @@ hipError_t as_iterate_view(fca_ctx* c, const DevState& s, int waves, int bpw, in
   return hipSuccess;
 }
 
+fca_status pre_iterate(fca_ctx* c) { return pre_check(c); }
 fca_status post_iterate(fca_ctx* c) { return post_check(c); }
 
 fca_status validate_init(fca_method method, int F, int N, int I, int J, const void* x, const void* v0,
@@ -422,7 +459,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   if (!c) return fail(nullptr, FCA_ERR_HIP, "host allocation failed");
   c->method = method; c->F = F; c->N = N; c->I = I; c->J = J;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->ks = ks; c->check_finite = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
+  c->ks = ks; c->check_finite = 0; c->params_checked = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
   c->split = 2; c->ev_fork = nullptr;
   for (int k = 0; k < 3; ++k) { c->side[k] = nullptr; c->ev_join[k] = nullptr; }
   c->backup = nullptr; c->arena = nullptr; c->last_waves = -1; c->last_bpw = -1;
@@ -443,10 +480,11 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   const bool em = method == FCA_METHOD_EM;
   const size_t o_R = em ? a.take<float2>(FJII) : 0;
   const size_t o_Ri = em ? a.take<float2>(FJII) : 0;
-  size_t nA = (size_t)F * s.nchunk * J * I;
+  size_t nA = (size_t)F * s.nchunk * J * (I + 1);  // eq. 20 sums S0 (J) and S1 (J I) per tile
   if (em) nA = (size_t)F * s.nchunk_em * J * I * I;
   const size_t o_pA = a.take<float>(nA);
   const size_t o_pB = em ? 0 : a.take<float>((size_t)F * s.nchunk * I * I * I);
+  const size_t o_pE = em ? 0 : a.take<float>((size_t)F * s.nchunk * J * (I * I + I));
   const size_t o_pL = a.take<double>((size_t)F * (s.nchunk > s.nchunk_em ? s.nchunk : s.nchunk_em));
   const size_t o_llf = a.take<double>(F);
   const size_t o_ll = a.take<double>(1);
@@ -468,6 +506,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   s.Rinv = em ? reinterpret_cast<float2*>(base + o_Ri) : nullptr;
   s.partA = reinterpret_cast<float*>(base + o_pA);
   s.partB = em ? nullptr : reinterpret_cast<float*>(base + o_pB);
+  s.partE = em ? nullptr : reinterpret_cast<float*>(base + o_pE);
   s.partL = reinterpret_cast<double*>(base + o_pL);
   s.llf = reinterpret_cast<double*>(base + o_llf);
   s.ll = reinterpret_cast<double*>(base + o_ll);
@@ -507,8 +546,10 @@ fca_status fastfca_as_iterate(fca_ctx* c, int n_iter) {
   if (c->method != FCA_METHOD_AS) return fail(c, FCA_ERR_STATE, "fastfca_as_iterate on an FCA EM context");
   if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
   if (n_iter == 0) return FCA_OK;
+  fca_status st = pre_check(c);
+  if (st != FCA_OK) return st;
   int w = 0, b = 0;
-  fca_status st = fca::as_iterate_chosen(c, n_iter, &w, &b);
+  st = fca::as_iterate_chosen(c, n_iter, &w, &b);
   if (st != FCA_OK) return st;
   return post_check(c);
 }
@@ -518,8 +559,10 @@ fca_status fca_em_iterate(fca_ctx* c, int n_iter) {
   if (c->method != FCA_METHOD_EM) return fail(c, FCA_ERR_STATE, "fca_em_iterate on a FastFCA-AS context");
   if (n_iter < 0) return fail(c, FCA_ERR_ARG, "n_iter must be >= 0");
   if (n_iter == 0) return FCA_OK;
+  fca_status st = pre_check(c);
+  if (st != FCA_OK) return st;
   Shape sh;
-  fca_status st = choose_shape(c, n_iter, &sh);
+  st = choose_shape(c, n_iter, &sh);
   if (st != FCA_OK) return st;
   c->last_waves = sh.waves; c->last_bpw = sh.bpw;
   ++c->version;
@@ -602,6 +645,7 @@ fca_status fca_set_params(fca_ctx* c, const float* v, const float* lam, const fc
   const DevState& s = c->s;
   hipError_t e = hipSuccess;
   ++c->version;
+  c->params_checked = 0;
   if (v) e = fca::launch_pack_v(v, s.vs, c->F, c->N, c->J, s.Npad, c->stream);
   if (e == hipSuccess && c->method == FCA_METHOD_AS && (lam || P_or_R)) {
     // lambda and P in one launch (a NULL one is skipped)
@@ -624,7 +668,9 @@ fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
     if (c->s.K != (int)value) ++c->version;  // a recorded forward run no longer describes the iteration
     c->s.K = (int)value;
   } else if (!std::strcmp(key, "p_update")) {
-    if (value < 0 || value > 2) return fail(c, FCA_ERR_ARG, "p_update must be 0 (fixed point), 1 (gradient) or 2 (natural gradient)");
+    if (value < 0 || value > 4)
+      return fail(c, FCA_ERR_ARG, "p_update must be 0 (fixed point), 1 (gradient), 2 (natural gradient), "
+                                  "3 (Newton) or 4 (EM with P in the M-step)");
     if (c->method != FCA_METHOD_AS && value != 0) return fail(c, FCA_ERR_STATE, "p_update applies to FastFCA-AS contexts");
     if (c->s.p_update != (int)value) ++c->version;
     c->s.p_update = (int)value;

@@ -1,7 +1,9 @@
 // Batched FastFCA-AS over many mixtures of uneven size (C ABI, declared in
 // include/fastfca.h).  Each mixture is an ordinary context; mixtures of equal
 // (I, J) form a group that advances in one launch of k_as_resident_batch over
-// a table of (mixture, bin) tiles sorted by decreasing N.  One batch step (all
+// a table of (mixture, bin) tiles sorted by decreasing N (one workgroup per
+// tile, or with the "queue" option persistent workgroups that take tiles
+// from a device counter).  One batch step (all
 // group launches) is captured once per iteration count into a HIP graph and
 // replayed.
 #include <hip/hip_runtime.h>
@@ -29,6 +31,8 @@ struct Group {
   int waves;                 // 0: the members use the streaming kernels
   DevState* d_states;        // device copies of the members' DevState
   int2* d_tiles;             // (member slot, bin), sorted by decreasing N
+  int* d_counter;            // the work queue's next tile ("queue" option)
+  mutable int queued;        // the last launch took the work-queue form
 };
 
 thread_local std::string g_batch_init_error;
@@ -53,6 +57,7 @@ struct fca_batch {
   std::vector<Group> groups;
   void* dev;  // one allocation for all group tables
   int use_graph;
+  int use_queue;  // 1: persistent workgroups take tiles from a device counter
   int autotune;
   int forced_waves;
   bool tuned;
@@ -84,8 +89,8 @@ hipError_t launch_group(fca_batch* b, const Group& g, int waves, int n_iter, hip
   for (int m : g.members) general = general || b->ctx[m]->s.K > 1 || b->ctx[m]->s.p_update != 0;
   for (int done = 0; done < n_iter;) {
     const int step = (n_iter - done) > 1024 ? 1024 : (n_iter - done);
-    hipError_t e =
-        g.ks->as_batch_resident(g.d_states, g.d_tiles, g.ntiles, g.n_max, st, step, waves, general);
+    hipError_t e = g.ks->as_batch_resident(g.d_states, g.d_tiles, g.ntiles, g.n_max, st, step, waves, general,
+                                           b->use_queue ? g.d_counter : nullptr, &g.queued);
     if (e != hipSuccess) return e;
     done += step;
   }
@@ -216,6 +221,7 @@ fca_status fca_batch_init(fca_batch** out, int n_mix, const int* F, const int* N
   for (int k = 0; k < kLanes; ++k) { b->lane[k] = nullptr; b->join[k] = nullptr; }
   b->dev = nullptr;
   b->use_graph = 1;
+  b->use_queue = 0;
   b->autotune = 1;
   b->forced_waves = 0;
   b->tuned = false;
@@ -252,6 +258,7 @@ fca_status fca_batch_init(fca_batch** out, int n_mix, const int* F, const int* N
   for (size_t k = 0; k < b->groups.size(); ++k) {
     off_s[k] = bytes; bytes += (sizeof(DevState) * b->groups[k].members.size() + 255) / 256 * 256;
     off_t[k] = bytes; bytes += (sizeof(int2) * (size_t)b->groups[k].ntiles + 255) / 256 * 256;
+    bytes += 256;  // the group's queue counter
   }
   hipError_t e = hipMalloc(&b->dev, bytes);
   if (e != hipSuccess) {
@@ -262,6 +269,8 @@ fca_status fca_batch_init(fca_batch** out, int n_mix, const int* F, const int* N
     Group& g = b->groups[k];
     g.d_states = reinterpret_cast<DevState*>(static_cast<char*>(b->dev) + off_s[k]);
     g.d_tiles = reinterpret_cast<int2*>(static_cast<char*>(b->dev) + off_t[k]);
+    g.d_counter = reinterpret_cast<int*>(static_cast<char*>(b->dev) + off_t[k] +
+                                         (sizeof(int2) * (size_t)g.ntiles + 255) / 256 * 256);
     std::vector<DevState> hs;
     for (int m : g.members) hs.push_back(b->ctx[m]->s);
     std::vector<int2> ht;
@@ -348,6 +357,10 @@ fca_status fca_batch_set_option(fca_batch* b, const char* key, long long value) 
   if (!std::strcmp(key, "graph")) {
     if (value != 0 && value != 1) return bfail(b, FCA_ERR_ARG, "graph must be 0 or 1");
     b->use_graph = (int)value;
+  } else if (!std::strcmp(key, "queue")) {
+    if (value != 0 && value != 1) return bfail(b, FCA_ERR_ARG, "queue must be 0 or 1");
+    b->use_queue = (int)value;
+    drop_graphs(b);
   } else if (!std::strcmp(key, "autotune")) {
     if (value != 0 && value != 1) return bfail(b, FCA_ERR_ARG, "autotune must be 0 or 1");
     b->autotune = (int)value;
@@ -381,12 +394,14 @@ fca_status fca_batch_get_option(fca_batch* b, const char* key, int group, long l
   if (!b) return bfail(nullptr, FCA_ERR_ARG, "NULL batch");
   if (!key || !value) return bfail(b, FCA_ERR_ARG, "NULL key or value");
   if (!std::strcmp(key, "groups")) { *value = (long long)b->groups.size(); return FCA_OK; }
+  if (!std::strcmp(key, "queue")) { *value = b->use_queue; return FCA_OK; }
   if (group < 0 || group >= (int)b->groups.size()) return bfail(b, FCA_ERR_ARG, "bad group index");
   const Group& g = b->groups[group];
   if (!std::strcmp(key, "group_I")) *value = g.I;
   else if (!std::strcmp(key, "group_J")) *value = g.J;
   else if (!std::strcmp(key, "group_tiles")) *value = g.ntiles;
   else if (!std::strcmp(key, "group_waves")) *value = b->tuned ? g.waves : -1;
+  else if (!std::strcmp(key, "group_queued")) *value = g.queued;
   else return bfail(b, FCA_ERR_ARG, std::string("unknown option '") + key + "'");
   return FCA_OK;
 }

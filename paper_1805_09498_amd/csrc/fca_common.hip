@@ -70,7 +70,7 @@ __global__ void k_check_finite(const float* __restrict__ a, long long n, int* fl
   const long long stride = (long long)gridDim.x * blockDim.x;
   bool bad = false;
   for (; t < n; t += stride) bad = bad || !isfinite(a[t]);
-  if (bad) atomicOr(flag, 1);
+  if (bad) atomicOr(flag, kFlagNonFinite);
 }
 
 // Deterministic sum of n doubles (the log-likelihood partials of every
@@ -86,6 +86,27 @@ __global__ void k_sum_f(const double* __restrict__ part, int n, double* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_check_positive(const float* __restrict__ vs, int F, int J, int N, int Npad,
+                                 const float* __restrict__ lam, long long n_lam, int* flag) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  const long long nv = (long long)F * J * Npad;
+  for (long long t = t0; t < nv; t += stride) {
+    const float x = vs[t];
+    bad = bad || ((t % Npad) < N && !(x > 0.f && isfinite(x)));
+  }
+  for (long long t = t0; t < n_lam; t += stride) {
+    const float x = lam[t];
+    bad = bad || !(x > 0.f && isfinite(x));
+  }
+  if (bad) atomicOr(flag, kFlagNonPositive);
+}
+
+__global__ void k_set_int(int* p, int value) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = value;
 }
 
 // Per-bin totals of per-tile partials: out[f] = sum_c part[f * nchunk + c],
@@ -137,6 +158,18 @@ hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream
 }
 hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, st, llf, F, out);
+  return hipGetLastError();
+}
+hipError_t launch_check_positive(const float* vs, int F, int J, int N, int Npad, const float* lam, long long n_lam,
+                                 int* flag, hipStream_t st) {
+  const long long n = (long long)F * J * Npad > n_lam ? (long long)F * J * Npad : n_lam;
+  long long b = (n + 255) / 256;
+  b = b < 1 ? 1 : (b > 4096 ? 4096 : b);
+  hipLaunchKernelGGL(k_check_positive, dim3((unsigned)b), dim3(256), 0, st, vs, F, J, N, Npad, lam, n_lam, flag);
+  return hipGetLastError();
+}
+hipError_t launch_set_flag(int* flag, int value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, flag, value);
   return hipGetLastError();
 }
 hipError_t launch_sum_chunks(const double* part, int F, int nchunk, double* out, hipStream_t st) {

@@ -215,7 +215,8 @@ __device__ inline bool lu_solve(T (&Mr)[I][I], T (&Mi)[I][I], T (&br)[I], T (&bi
 // Cholesky factor of a Hermitian positive-definite matrix given by its upper
 // triangle: A = L L^H with L lower triangular and real positive diagonal.
 // On return Lr/Li hold L (strictly-upper part unused) and dinv the
-// reciprocal diagonal.  Returns false if A is not numerically PD.
+// reciprocal diagonal.  Returns false if a pivot is <= 0 (A not numerically
+// positive definite).
 template <int I, typename T = float>
 __device__ inline bool cholesky(const T (&Ar)[I][I], const T (&Ai)[I][I],
                                 T (&Lr)[I][I], T (&Li)[I][I], T (&dinv)[I]) {
@@ -225,7 +226,7 @@ __device__ inline bool cholesky(const T (&Ar)[I][I], const T (&Ai)[I][I],
     T s = Ar[k][k];
 #pragma unroll
     for (int m = 0; m < k; ++m) s -= Lr[k][m] * Lr[k][m] + Li[k][m] * Li[k][m];
-    ok = ok && (s > T(0));
+    ok = ok && !(s <= T(0));  // NaN passes: it is reported as a non-finite value instead
     const T dk = sqrtT(s > T(1e-37) ? s : T(1e-37));
     const T ik = rcpT(dk);
     Lr[k][k] = dk; Li[k][k] = T(0); dinv[k] = ik;
@@ -438,7 +439,10 @@ __device__ __forceinline__ void pinvh_col(const float (&Pr)[I][I], const float (
 
 // Solve Q p = b for a Hermitian positive-definite Q given by its upper
 // triangle (Qr[a][b], Qi[a][b] for a <= b).  I <= 2: adjugate / determinant;
-// I = 3: LDL^H; larger I: Cholesky.  b is overwritten with p.
+// I = 3: LDL^H; larger I: Cholesky.  b is overwritten with p.  Returns false
+// when a pivot (or, for I = 2, the determinant) is <= 0: Q is not
+// numerically positive definite.  A NaN pivot returns true (the result is
+// reported as a non-finite value instead).
 //
 // Why not the 3x3 adjugate: near DC a diffuse field makes Q nearly rank one.
 // The 2x2 minors of such a matrix cancel to O(lambda_1 lambda_2) from terms
@@ -448,20 +452,23 @@ __device__ __forceinline__ void pinvh_col(const float (&Pr)[I][I], const float (
 // adjugate entries are entries of Q and only the determinant cancels, which
 // also costs cond(Q) eps.
 template <int I, typename T = float>
-__device__ __forceinline__ void herm_solve(const T (&Qr)[I][I], const T (&Qi)[I][I],
+__device__ __forceinline__ bool herm_solve(const T (&Qr)[I][I], const T (&Qi)[I][I],
                                            T (&br)[I], T (&bi)[I]) {
   if constexpr (I == 1) {
     const T iq = rcpT(Qr[0][0]);
     br[0] *= iq; bi[0] *= iq;
+    return !(Qr[0][0] <= T(0));
   } else if constexpr (I == 2) {
     const T a = Qr[0][0], d = Qr[1][1], xr = Qr[0][1], xi = Qi[0][1];
-    const T idet = rcpT(a * d - (xr * xr + xi * xi));
+    const T det = a * d - (xr * xr + xi * xi);
+    const T idet = rcpT(det);
     // adj = [[d, -x], [-conj(x), a]]
     const T p0r = d * br[0] - (xr * br[1] - xi * bi[1]);
     const T p0i = d * bi[0] - (xr * bi[1] + xi * br[1]);
     const T p1r = a * br[1] - (xr * br[0] + xi * bi[0]);
     const T p1i = a * bi[1] - (xr * bi[0] - xi * br[0]);
     br[0] = p0r * idet; bi[0] = p0i * idet; br[1] = p1r * idet; bi[1] = p1i * idet;
+    return !(a <= T(0) || det <= T(0));
   } else if constexpr (I == 3) {
     // Q = L D L^H, L unit lower triangular; with Q = [[a, x, y], [., d, z],
     // [., ., g]] the lower entries are conj(x), conj(y), conj(z).
@@ -488,26 +495,32 @@ __device__ __forceinline__ void herm_solve(const T (&Qr)[I][I], const T (&Qi)[I]
     br[0] = w0r * id0 - (l10r * p1r + l10i * p1i) - (l20r * p2r + l20i * p2i);
     bi[0] = w0i * id0 - (l10r * p1i - l10i * p1r) - (l20r * p2i - l20i * p2r);
     br[1] = p1r; bi[1] = p1i; br[2] = p2r; bi[2] = p2i;
+    return !(d0 <= T(0) || d1 <= T(0) || d2 <= T(0));
   } else {
     T Lr[I][I], Li[I][I], dinv[I];
-    cholesky<I, T>(Qr, Qi, Lr, Li, dinv);
+    const bool ok = cholesky<I, T>(Qr, Qi, Lr, Li, dinv);
     cholesky_solve<I, T>(Lr, Li, dinv, br, bi);
+    return ok;
   }
 }
 
 // Inverse of a Hermitian positive-definite matrix given by its upper triangle
 // (full result in Xr/Xi).  I <= 3: adjugate / determinant; larger I:
-// Cholesky.
+// Cholesky.  Returns false when the matrix is not numerically positive
+// definite (a leading principal minor <= 0).
 template <int I, typename T = float>
-__device__ __forceinline__ void herm_inv(const T (&Ar)[I][I], const T (&Ai)[I][I],
+__device__ __forceinline__ bool herm_inv(const T (&Ar)[I][I], const T (&Ai)[I][I],
                                          T (&Xr)[I][I], T (&Xi)[I][I]) {
   if constexpr (I == 1) {
     Xr[0][0] = rcpT(Ar[0][0]); Xi[0][0] = T(0);
+    return !(Ar[0][0] <= T(0));
   } else if constexpr (I == 2) {
     const T a = Ar[0][0], d = Ar[1][1], xr = Ar[0][1], xi = Ai[0][1];
-    const T id = rcpT(a * d - (xr * xr + xi * xi));
+    const T det = a * d - (xr * xr + xi * xi);
+    const T id = rcpT(det);
     Xr[0][0] = d * id; Xi[0][0] = T(0); Xr[1][1] = a * id; Xi[1][1] = T(0);
     Xr[0][1] = -xr * id; Xi[0][1] = -xi * id; Xr[1][0] = -xr * id; Xi[1][0] = xi * id;
+    return !(a <= T(0) || det <= T(0));
   } else if constexpr (I == 3) {
     const T a = Ar[0][0], d = Ar[1][1], g = Ar[2][2];
     const T xr = Ar[0][1], xi = Ai[0][1], yr = Ar[0][2], yi = Ai[0][2], zr = Ar[1][2], zi = Ai[1][2];
@@ -515,13 +528,15 @@ __device__ __forceinline__ void herm_inv(const T (&Ar)[I][I], const T (&Ai)[I][I
     const T A01r = (yr * zr + yi * zi) - xr * g, A01i = (yi * zr - yr * zi) - xi * g;
     const T A02r = (xr * zr - xi * zi) - yr * d, A02i = (xr * zi + xi * zr) - yi * d;
     const T A12r = (yr * xr + yi * xi) - a * zr, A12i = (yi * xr - yr * xi) - a * zi;
-    const T id = rcpT(a * A00 + (xr * A01r + xi * A01i) + (yr * A02r + yi * A02i));
+    const T det = a * A00 + (xr * A01r + xi * A01i) + (yr * A02r + yi * A02i);
+    const T id = rcpT(det);
     Xr[0][0] = A00 * id; Xi[0][0] = T(0); Xr[1][1] = A11 * id; Xi[1][1] = T(0); Xr[2][2] = A22 * id; Xi[2][2] = T(0);
     Xr[0][1] = A01r * id; Xi[0][1] = A01i * id; Xr[1][0] = A01r * id; Xi[1][0] = -A01i * id;
     Xr[0][2] = A02r * id; Xi[0][2] = A02i * id; Xr[2][0] = A02r * id; Xi[2][0] = -A02i * id;
     Xr[1][2] = A12r * id; Xi[1][2] = A12i * id; Xr[2][1] = A12r * id; Xi[2][1] = -A12i * id;
+    return !(a <= T(0) || A22 <= T(0) || det <= T(0));
   } else {
-    herm_inverse<I, T>(Ar, Ai, Xr, Xi);
+    return herm_inverse<I, T>(Ar, Ai, Xr, Xi);
   }
 }
 

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_em_resident(DevState s, int n_
     for (int k = 0; k < NPT; ++k) {
       if (wbase + k * T < s.N) {
         const bool ok = threadIdx.x + k * T < s.N;
-        em_point<I, J>(sh, xr[k], xi[k], v[k], H, ok);
+        if (!em_point<I, J>(sh, xr[k], xi[k], v[k], H, ok)) atomicOr(s.flag, kFlagSingular);
       }
     }
     float flat[J * I * I];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kResMaxBlock) void k_em_resident(DevState s, int n_
 #pragma unroll
         for (int b = a + 1; b < I; ++b) { Rr[b][a] = Rr[a][b]; Ri[b][a] = -Ri[a][b]; }
       }
-      herm_inv<I>(Rr, Ri, Xr, Xi);
+      if (!herm_inv<I>(Rr, Ri, Xr, Xi)) atomicOr(s.flag, kFlagSingular);
 #pragma unroll
       for (int a = 0; a < I; ++a)
 #pragma unroll

@@ -16,6 +16,7 @@ struct fca_ctx {
   fca::DevState s;
   void* arena;
   int check_finite;
+  int params_checked;  // with check_finite: the parameters passed the device check since fca_init / fca_set_params
   int path;   // 0 auto, 1 resident, 2 streaming
   int waves;  // 0 auto
   int bpw;    // bins per workgroup of the resident AS kernel, 0 auto
@@ -58,7 +59,12 @@ fca_status as_iterate_chosen_trace(fca_ctx* c, int n_iter, const Trace& tr, int*
 // n_iter FastFCA-AS iterations of the state view s (the context's x and
 // scratch, any v / lambda / P) with a given launch shape.
 hipError_t as_iterate_view(fca_ctx* c, const DevState& s, int waves, int bpw, int n_iter);
-// After-launch checks of an iterate call (launch error, optional finiteness).
+// Before the launches of an iterate call: with "check_finite", the device
+// check of the parameters (once after fca_init / fca_set_params) and the
+// clearing of the flag the iteration kernels report into.
+fca_status pre_iterate(fca_ctx* c);
+// After-launch checks of an iterate call (launch error; with "check_finite"
+// a non-positive-definite solve or a non-finite parameter).
 fca_status post_iterate(fca_ctx* c);
 
 // The host-side argument checks of fca_init (no device access).

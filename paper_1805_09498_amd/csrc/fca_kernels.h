@@ -14,6 +14,7 @@
 
 #include "fca_device.h"
 #include "fca_point.h"
+#include "fca_pvariants.h"
 #include "fca_state.h"
 
 namespace fca {
@@ -92,15 +93,16 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float4 sPt[I * kPH<I>];
   __shared__ float sLam[J * I];
-  __shared__ float red[(kBlock / kWave) * pad4(J * I)];
+  constexpr int V = kEq20Sums<I, J>;
+  __shared__ float red[(kBlock / kWave) * pad4(V)];
   stage_P_columns<I>(s.P + (size_t)f * I * I, sPt);
   for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
   __syncthreads();
-  float lam[J][I];
+  float lam[J][I], lamI[J][I];
 #pragma unroll
   for (int j = 0; j < J; ++j)
 #pragma unroll
-    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+    for (int i = 0; i < I; ++i) { lam[j][i] = sLam[j * I + i]; lamI[j][i] = lam[j][i] * (1.0f / float(I)); }
   float Pr[kStreamPinLds<I> ? 1 : I][kStreamPinLds<I> ? 1 : I], Pi[kStreamPinLds<I> ? 1 : I][kStreamPinLds<I> ? 1 : I];
   if constexpr (!kStreamPinLds<I>) {
 #pragma unroll
@@ -112,11 +114,13 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
         if (2 * h + 1 < I) { Pr[2 * h + 1][i] = q.z; Pi[2 * h + 1][i] = q.w; }
       }
   }
-  float S[J][I];
+  float S0[J], S1[J][I];
 #pragma unroll
-  for (int j = 0; j < J; ++j)
+  for (int j = 0; j < J; ++j) {
+    S0[j] = 0.f;
 #pragma unroll
-    for (int i = 0; i < I; ++i) S[j][i] = 0.f;
+    for (int i = 0; i < I; ++i) S1[j][i] = 0.f;
+  }
 
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   float* vf = s.vs + (size_t)f * J * s.Npad;
@@ -143,18 +147,33 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
     }
 #pragma unroll
     for (int i = 0; i < I; ++i) y2[i] = fmaf(yr[i], yr[i], yi[i] * yi[i]);
-    as_point_em<I, J>(y2, lam, v, S, ok);
+    as_point_em<I, J>(y2, lam, lamI, v, S0, S1, ok);
     if (ok) {
 #pragma unroll
       for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[j];
     }
   }
-  float flat[J * I];
+  float flat[V];
 #pragma unroll
-  for (int j = 0; j < J; ++j)
+  for (int j = 0; j < J; ++j) {
+    flat[j] = S0[j];
 #pragma unroll
-    for (int i = 0; i < I; ++i) flat[j * I + i] = S[j][i];
-  block_totals_store<J * I>(flat, s.partA + ((size_t)f * s.nchunk + chunk) * J * I, red);
+    for (int i = 0; i < I; ++i) flat[J + j * I + i] = S1[j][i];
+  }
+  block_totals_store<V>(flat, s.partA + ((size_t)f * s.nchunk + chunk) * V, red);
+}
+
+// lambda' of eq. 20 for entry t = j I + i of bin f from the tiles' S0, S1.
+template <int I, int J>
+__device__ __forceinline__ float eq20_from_tiles(const DevState& s, int f, int t, float lam, float invN) {
+  constexpr int V = kEq20Sums<I, J>;
+  float s0 = 0.f, s1 = 0.f;
+  for (int c = 0; c < s.nchunk; ++c) {
+    const float* src = s.partA + ((size_t)f * s.nchunk + c) * V;
+    s0 += src[t / I];
+    s1 += src[J + t];
+  }
+  return eq20_lambda(lam, s0, s1, invN);
 }
 
 // Pass B: lambda (eq. 20) from the tile sums of pass A, then the tile's
@@ -195,11 +214,8 @@ __global__ __launch_bounds__(PassBLayout<I>::kThreads) void k_as_pass_b(DevState
   __shared__ float4 sPt[I * kPH<I>];
   __shared__ float sRec[L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
   const float invN = 1.0f / float(s.N);
-  for (int t = threadIdx.x; t < J * I; t += L::kThreads) {
-    float acc = 0.f;
-    for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + t];
-    sLam[t] = acc * (s.lam[(size_t)f * J * I + t] * invN);  // eq. 20
-  }
+  for (int t = threadIdx.x; t < J * I; t += L::kThreads)
+    sLam[t] = eq20_from_tiles<I, J>(s, f, t, s.lam[(size_t)f * J * I + t], invN);  // eq. 20
   stage_P_columns<I>(s.P + (size_t)f * I * I, sPt);  // the old P (k_as_solve replaces it after this pass)
   __syncthreads();
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
@@ -365,19 +381,22 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
     // lambda update (eq. 20): column i of every Lambda_j.
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      float acc = 0.f;
-      for (int c = 0; c < s.nchunk; ++c) acc += s.partA[((size_t)f * s.nchunk + c) * J * I + j * I + i];
       float* l = s.lam + (size_t)f * J * I + j * I + i;
-      *l = acc * ((*l) * invN);  // eq. 20 (old lambda times the scaled sum)
+      *l = eq20_from_tiles<I, J>(s, f, j * I + i, *l, invN);  // eq. 20
     }
-    // S_i from the tile partials.
+    // S_i from the tile partials (EM with P in the M-step uses other sums).
     float A[I * I];
 #pragma unroll
     for (int k = 0; k < I * I; ++k) A[k] = 0.f;
-    for (int c = 0; c < s.nchunk; ++c) {
+    for (int c = 0; c < (s.p_update == 4 ? 0 : s.nchunk); ++c) {
       const float* src = s.partB + ((size_t)f * s.nchunk + c) * I * I * I + i * I * I;
 #pragma unroll
       for (int k = 0; k < I * I; ++k) A[k] += src[k];
+    }
+    if (s.p_update == 3) {  // Newton's step: the totals go to the first tile's slot for k_as_newton
+      float* dst = s.partB + (size_t)f * s.nchunk * I * I * I + i * I * I;
+#pragma unroll
+      for (int k = 0; k < I * I; ++k) dst[k] = A[k];
     }
 #pragma unroll
     for (int a = 0; a < I; ++a) {
@@ -389,6 +408,7 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
       }
     }
   }
+  if (s.p_update >= 3) return;  // Newton / EM with P in the M-step: k_as_newton / k_as_emp_step
   // gamma_i = S_i e_i / N (column i of G_i) for the gradient-type P steps
   float gr[I], gi[I];
 #pragma unroll
@@ -415,7 +435,7 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
       } else if (kk == 0) {
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] = (a == i) ? fN : 0.f; ai[a] = 0.f; }
-        herm_solve<I>(Sr, Si, ar, ai);
+        if (!herm_solve<I>(Sr, Si, ar, ai)) atomicOr(s.flag, kFlagSingular);
       } else {
         float Ar[I][I], Ai[I][I];
 #pragma unroll
@@ -425,7 +445,7 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
         pinvh_col<I, float>(Ar, Ai, i, ar, ai);   // column i of A^-H
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
-        herm_solve<I>(Sr, Si, ar, ai);
+        if (!herm_solve<I>(Sr, Si, ar, ai)) atomicOr(s.flag, kFlagSingular);
       }
     }
     __syncthreads();
@@ -481,9 +501,14 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
 template <int I, int J>
 hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
   dim3 grid(s.nchunk, s.F);
+  // EM with P in the M-step: its sums need the v before pass A overwrites it
+  if (s.p_update == 4) hipLaunchKernelGGL((k_as_pass_emp<I, J>), dim3(s.nchunk, s.F, J), dim3(kBlock), 0, st, s);
   hipLaunchKernelGGL((k_as_pass_a<I, J>), grid, dim3(kBlock), 0, st, s);
-  hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+  if (s.p_update != 4)
+    hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
   hipLaunchKernelGGL((k_as_solve<I, J>), dim3((s.F + 7) / 8), dim3(64), 0, st, s);
+  if (s.p_update == 3) hipLaunchKernelGGL((k_as_newton<I, J>), dim3(s.F), dim3(kNewtonThreads), 0, st, s);
+  if (s.p_update == 4) hipLaunchKernelGGL((k_as_emp_step<I, J>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
   return hipGetLastError();
 }
 
@@ -596,11 +621,22 @@ hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
 // ----------------------------------------------------------------------------
 // Wiener filter (eq. 3; AS form x_j = P^-H (g_j o y) from eq. 15-16).
 // ----------------------------------------------------------------------------
-template <int I, int J>
+// Output-bound: 8IJ bytes written per point.  A wave's 64 consecutive frames
+// of one source are 64 I contiguous complex values in [J][F][N][I]; each
+// lane's I values go to a wave-private LDS tile and come back as
+// consecutive 16-byte chunks (8-byte ones for odd I or an output not
+// 16-byte aligned), so every store instruction writes whole cache lines.
+// Up to I = 6 P and B = P^-H sit in registers; above, they are read from LDS
+// at each use (their 2 x 128 values in registers left one wave per SIMD).
+template <int I>
+constexpr bool kWienerPinLds = (I >= 7);
+
+template <int I, int J, bool kVec4>
 __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __restrict__ out) {
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float2 sP[I * I], sB[I * I];
   __shared__ float sLam[J * I];
+  __shared__ float2 sOut[kBlock / kWave][kWave * I];
   for (int t = threadIdx.x; t < I * I; t += kBlock) sP[t] = s.P[(size_t)f * I * I + t];
   for (int t = threadIdx.x; t < J * I; t += kBlock) sLam[t] = s.lam[(size_t)f * J * I + t];
   __syncthreads();
@@ -618,58 +654,106 @@ __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __rest
     for (int r = 0; r < I; ++r) sB[r * I + c] = make_float2(br[r], bi[r]);
   }
   __syncthreads();
-  float Pr[I][I], Pi[I][I], Br[I][I], Bi[I][I], lam[J][I];
-  load_P<I>(sP, Pr, Pi);
-  load_P<I>(sB, Br, Bi);
-#pragma unroll
-  for (int j = 0; j < J; ++j)
-#pragma unroll
-    for (int i = 0; i < I; ++i) lam[j][i] = sLam[j * I + i];
+  constexpr bool kLds = kWienerPinLds<I>;
+  float Pr[kLds ? 1 : I][I], Pi[kLds ? 1 : I][I], Br[kLds ? 1 : I][I], Bi[kLds ? 1 : I][I];
+  if constexpr (!kLds) {
+    load_P<I>(sP, Pr, Pi);
+    load_P<I>(sB, Br, Bi);
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  float2* tile = sOut[wave];
   const float* xf = s.xs + (size_t)f * 2 * I * s.Npad;
   const float* vf = s.vs + (size_t)f * J * s.Npad;
-#pragma unroll
+#pragma unroll 1
   for (int p = 0; p < kPts; ++p) {
-    const int n = chunk * kChunk + p * kBlock + threadIdx.x;
-    if (n >= s.N) continue;
+    const int n0 = chunk * kChunk + p * kBlock + wave * kWave;  // the wave's first frame
+    if (n0 >= s.N) break;                                       // wave-uniform
+    const int n = n0 + lane;
+    const bool ok = n < s.N;
+    const int nn = ok ? n : n0;
     float xr[I], xi[I], v[J], yr[I], yi[I], id[I];
 #pragma unroll
-    for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + n]; xi[i] = xf[(size_t)(I + i) * s.Npad + n]; }
+    for (int i = 0; i < I; ++i) { xr[i] = xf[(size_t)i * s.Npad + nn]; xi[i] = xf[(size_t)(I + i) * s.Npad + nn]; }
 #pragma unroll
-    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + n];
-    as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+    for (int j = 0; j < J; ++j) v[j] = vf[(size_t)j * s.Npad + nn];
+    if constexpr (kLds) {
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        float a = 0.f, b = 0.f;
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+          const float2 pk = sP[k * I + i];
+          a = fmaf(pk.x, xr[k], a); a = fmaf(pk.y, xi[k], a);
+          b = fmaf(pk.x, xi[k], b); b = fmaf(-pk.y, xr[k], b);
+        }
+        yr[i] = a; yi[i] = b;
+      }
+    } else {
+      as_transform<I>(Pr, Pi, xr, xi, yr, yi);
+    }
 #pragma unroll
     for (int i = 0; i < I; ++i) {
       float d = 0.f;
 #pragma unroll
-      for (int j = 0; j < J; ++j) d = fmaf(v[j], lam[j][i], d);
+      for (int j = 0; j < J; ++j) d = fmaf(v[j], sLam[j * I + i], d);
       id[i] = 1.0f / d;
     }
-#pragma unroll
+    const int rows = (s.N - n0 < kWave ? s.N - n0 : kWave) * I;  // valid complex values of the wave
+#pragma unroll 1
     for (int j = 0; j < J; ++j) {
+      // v_j and lambda_j by selection and from LDS (a uniform address): a
+      // register array indexed by the loop counter is placed in scratch memory
+      float vj = v[0];
+#pragma unroll
+      for (int q = 1; q < J; ++q) vj = (j == q) ? v[q] : vj;
       float ur[I], ui[I];
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        const float g = v[j] * lam[j][i] * id[i];
+        const float g = vj * sLam[j * I + i] * id[i];
         ur[i] = g * yr[i]; ui[i] = g * yi[i];
       }
-      float2* o = out + (((size_t)j * s.F + f) * s.N + n) * I;
 #pragma unroll
       for (int a = 0; a < I; ++a) {
         float sr = 0.f, si = 0.f;
 #pragma unroll
         for (int i = 0; i < I; ++i) {
-          sr = fmaf(Br[a][i], ur[i], sr); sr = fmaf(-Bi[a][i], ui[i], sr);
-          si = fmaf(Br[a][i], ui[i], si); si = fmaf(Bi[a][i], ur[i], si);
+          float br, bi;
+          if constexpr (kLds) { const float2 b = sB[a * I + i]; br = b.x; bi = b.y; }
+          else { br = Br[a][i]; bi = Bi[a][i]; }
+          sr = fmaf(br, ur[i], sr); sr = fmaf(-bi, ui[i], sr);
+          si = fmaf(br, ui[i], si); si = fmaf(bi, ur[i], si);
         }
-        o[a] = make_float2(sr, si);
+        tile[lane * I + a] = make_float2(sr, si);
       }
+      __builtin_amdgcn_wave_barrier();
+      float2* o = out + (((size_t)j * s.F + f) * s.N + n0) * I;
+      if constexpr (kVec4) {
+        const float4* t4 = reinterpret_cast<const float4*>(tile);
+        float4* o4 = reinterpret_cast<float4*>(o);
+#pragma unroll
+        for (int r = 0; r < I / 2; ++r) {
+          const int q = lane + r * kWave;
+          if (2 * q < rows) o4[q] = t4[q];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < I; ++r) {
+          const int q = lane + r * kWave;
+          if (q < rows) o[q] = tile[q];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
 }
 
 template <int I, int J>
 hipError_t launch_as_wiener(const DevState& s, hipStream_t st, float2* out) {
-  hipLaunchKernelGGL((k_as_wiener<I, J>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s, out);
+  const bool vec4 = (I % 2 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+  if (vec4)
+    hipLaunchKernelGGL((k_as_wiener<I, J, true>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s, out);
+  else
+    hipLaunchKernelGGL((k_as_wiener<I, J, false>), dim3(s.nchunk, s.F), dim3(kBlock), 0, st, s, out);
   return hipGetLastError();
 }
 
@@ -712,13 +796,15 @@ __device__ __forceinline__ void em_model_cov(const EmShared<I, J>& sh, const flo
 // inverse C^-1 and two I x I products per source (S_j C^-1 and (S_j C^-1) S_j),
 // the v update (eq. 9, current S_j) and the summand of eq. 10 (new v_j),
 // Rhat_j / v_j in packed Hermitian slots, added to H[j] (nothing if !ok).
+// Returns false for a point (with ok) whose C is not numerically positive
+// definite.
 template <int I, int J>
-__device__ __forceinline__ void em_point(const EmShared<I, J>& sh, const float (&xr)[I],
+__device__ __forceinline__ bool em_point(const EmShared<I, J>& sh, const float (&xr)[I],
                                          const float (&xi)[I], float (&v)[J], float (&H)[J][I * I],
                                          bool ok) {
   float Cr[I][I], Ci[I][I], Xr[I][I], Xi[I][I];
   em_model_cov<I, J>(sh, v, Cr, Ci);
-  herm_inv<I>(Cr, Ci, Xr, Xi);  // C^-1 (one inversion per point)
+  const bool pd = herm_inv<I>(Cr, Ci, Xr, Xi);  // C^-1 (one inversion per point)
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     // K = S_j C^-1 (first product); W_j = v_j K.
@@ -786,6 +872,7 @@ __device__ __forceinline__ void em_point(const EmShared<I, J>& sh, const float (
         if (b > a) H[j][b * I + a] = fmaf(Hi[a][b], iv, H[j][b * I + a]);
       }
   }
+  return pd || !ok;
 }
 
 // Streaming FCA EM pass: one point per lane; per source the summands of
@@ -815,7 +902,7 @@ __global__ __launch_bounds__(kBlock) void k_em_pass(DevState s) {
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int q = 0; q < I * I; ++q) H[j][q] = 0.f;
-  em_point<I, J>(sh, xr, xi, v, H, ok);
+  if (!em_point<I, J>(sh, xr, xi, v, H, ok)) atomicOr(s.flag, kFlagSingular);
   if (ok) {
 #pragma unroll
     for (int j = 0; j < J; ++j) vf[(size_t)j * s.Npad + n] = v[j];
@@ -859,7 +946,7 @@ __global__ __launch_bounds__(64) void k_em_finalize(DevState s) {
       Rr[b][a] = Rr[a][b]; Ri[b][a] = -Ri[a][b];
     }
   }
-  herm_inv<I>(Rr, Ri, Xr, Xi);
+  if (!herm_inv<I>(Rr, Ri, Xr, Xi)) atomicOr(s.flag, kFlagSingular);
   float2* R = s.R + ((size_t)f * J + j) * I * I;
   float2* X = s.Rinv + ((size_t)f * J + j) * I * I;
 #pragma unroll
@@ -1051,6 +1138,87 @@ __global__ __launch_bounds__(kBlock) void k_em_wiener(DevState s, float2* __rest
 template <int I, int J>
 hipError_t launch_em_wiener(const DevState& s, hipStream_t st, float2* out) {
   hipLaunchKernelGGL((k_em_wiener<I, J>), dim3(s.nchunk_em, s.F), dim3(kBlock), 0, st, s, out);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Parameter check (option "check_finite"): the model needs v > 0, lambda > 0
+// and a non-singular P(f) (Section 3.1 and eq. 12), or S_j(f) positive
+// definite for FCA.  v and lambda are checked by k_check_positive
+// (fca_common.hip); this kernel checks the matrices, one lane per bin (AS)
+// or per (bin, source) (EM), and sets kFlagSingularParam.
+// ----------------------------------------------------------------------------
+template <int I, int J>
+__global__ __launch_bounds__(64) void k_check_matrices(DevState s, int em) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!em) {
+    if (t >= s.F) return;
+    // Gaussian elimination with partial pivoting on P(f): singular when a
+    // pivot's modulus falls to I * 2^-23 of the largest entry's (P is
+    // singular to working precision) or is NaN.
+    float Mr[I][I], Mi[I][I], big = 0.f;
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) {
+        const float2 z = s.P[(size_t)t * I * I + a * I + b];
+        Mr[a][b] = z.x; Mi[a][b] = z.y;
+        big = fmaxf(big, z.x * z.x + z.y * z.y);
+      }
+    const float tol = float(I) * float(I) * 1.42108547e-14f * big;  // (I 2^-23)^2 |max|^2
+    bool ok = big > 0.f;
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+#pragma unroll
+      for (int r = k + 1; r < I; ++r) {
+        const float cur = Mr[k][k] * Mr[k][k] + Mi[k][k] * Mi[k][k];
+        const float cand = Mr[r][k] * Mr[r][k] + Mi[r][k] * Mi[r][k];
+        if (cand > cur) {
+#pragma unroll
+          for (int c = 0; c < I; ++c) {
+            float u = Mr[k][c]; Mr[k][c] = Mr[r][c]; Mr[r][c] = u;
+            u = Mi[k][c]; Mi[k][c] = Mi[r][c]; Mi[r][c] = u;
+          }
+        }
+      }
+      const float pr = Mr[k][k], pi = Mi[k][k];
+      const float den = pr * pr + pi * pi;
+      ok = ok && (den > tol);
+      const float inv = rcp(den > tol ? den : 1.f);
+      const float qr = pr * inv, qi = -pi * inv;
+#pragma unroll
+      for (int r = k + 1; r < I; ++r) {
+        const float lr = Mr[r][k] * qr - Mi[r][k] * qi;
+        const float li = Mr[r][k] * qi + Mi[r][k] * qr;
+#pragma unroll
+        for (int c = k + 1; c < I; ++c) {
+          Mr[r][c] -= lr * Mr[k][c] - li * Mi[k][c];
+          Mi[r][c] -= lr * Mi[k][c] + li * Mr[k][c];
+        }
+      }
+    }
+    if (!ok) atomicOr(s.flag, kFlagSingularParam);
+  } else {
+    if (t >= s.F * J) return;
+    float Ar[I][I], Ai[I][I], Lr[I][I], Li[I][I], dinv[I];
+    const float2* R = s.R + (size_t)t * I * I;
+    bool fin = true;
+#pragma unroll
+    for (int a = 0; a < I; ++a)
+#pragma unroll
+      for (int b = 0; b < I; ++b) {
+        const float2 z = R[a * I + b];
+        Ar[a][b] = z.x; Ai[a][b] = z.y;
+        fin = fin && isfinite(z.x) && isfinite(z.y);
+      }
+    if (!fin || !cholesky<I>(Ar, Ai, Lr, Li, dinv)) atomicOr(s.flag, kFlagSingularParam);
+  }
+}
+
+template <int I, int J>
+hipError_t launch_check_matrices(const DevState& s, hipStream_t st, int em) {
+  const int n = em ? s.F * J : s.F;
+  hipLaunchKernelGGL((k_check_matrices<I, J>), dim3((n + 63) / 64), dim3(64), 0, st, s, em);
   return hipGetLastError();
 }
 

@@ -56,13 +56,16 @@ __device__ __forceinline__ void as_transform(const float (&Pr)[I][I], const floa
 //   (|mu~_ji|^2 + phi~_ji) / (v_j lambda_ji) = 1 - g_ji + g_ji |y_i|^2 / d_i
 //                                            = 1 + v_j lambda_ji e_i =: r_ji,
 //   with e_i = (|y_i|^2 / d_i - 1) / d_i;
-//   v_j <- (1/I) sum_i v_j r_ji = v_j W_j,  W_j = 1 + (v_j / I) sum_i lambda_ji e_i  (eq. 19),
-//   summand of eq. 20:  (|mu~|^2 + phi~)_ji / v_j(new) = lambda_ji r_ji / W_j.
-// The point adds r_ji / W_j to S_ji and updates v (when `take`); the caller
-// applies the factor lambda_ji / N once per bin after summing over the frames.
+//   v_j <- (1/I) sum_i v_j r_ji = v_j W_j,  W_j = 1 + v_j sum_i (lambda_ji / I) e_i  (eq. 19),
+//   summand of eq. 20:  (|mu~|^2 + phi~)_ji / v_j(new) = lambda_ji r_ji / W_j
+//                     = lambda_ji (1 / W_j + lambda_ji (v_j / W_j) e_i).
+// The point adds 1 / W_j to S0[j] and (v_j / W_j) e_i to S1[j][i] (nothing
+// when `take` is false) and updates v; after the frame sums the caller forms
+// lambda_ji (S0_j + lambda_ji S1_ji) / N once per bin.  lamI = lambda / I.
 template <int I, int J>
 __device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&lam)[J][I],
-                                            float (&v)[J], float (&S)[J][I], bool take) {
+                                            const float (&lamI)[J][I], float (&v)[J], float (&S0)[J],
+                                            float (&S1)[J][I], bool take) {
   float e[I];
 #pragma unroll
   for (int i = 0; i < I; ++i) {
@@ -74,18 +77,28 @@ __device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&
   }
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    float le[I];
-    float u = 0.f;
+    float u = lamI[j][0] * e[0];
 #pragma unroll
-    for (int i = 0; i < I; ++i) { le[i] = lam[j][i] * e[i]; u += le[i]; }
-    const float W = fmaf(v[j] * (1.0f / float(I)), u, 1.0f);
+    for (int i = 1; i < I; ++i) u = fmaf(lamI[j][i], e[i], u);
+    const float W = fmaf(v[j], u, 1.0f);
     // A lane that does not own a frame (take = false) keeps its v, so that
     // padded lanes stay finite over any number of iterations.
     const float rW = take ? rcp(W) : 0.f;
+    const float m = v[j] * rW;
+    S0[j] += rW;
 #pragma unroll
-    for (int i = 0; i < I; ++i) S[j][i] = fmaf(fmaf(v[j], le[i], 1.0f), rW, S[j][i]);
+    for (int i = 0; i < I; ++i) S1[j][i] = fmaf(m, e[i], S1[j][i]);
     v[j] = take ? v[j] * W : v[j];
   }
+}
+
+// Number of eq. 20 partial sums per bin or tile: S0 (J), then S1 (J x I).
+template <int I, int J>
+constexpr int kEq20Sums = J + J * I;
+
+// lambda' = lambda (S0_j + lambda S1_ji) / N from the summed S0, S1 (eq. 20).
+__device__ __forceinline__ float eq20_lambda(float lam, float s0, float s1, float invN) {
+  return (lam * invN) * fmaf(lam, s1, s0);
 }
 
 // 1 / d_i with d_i = sum_j v_j lambda_ji (the weights of eq. 23).

@@ -74,7 +74,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
                                                  const Trace& tr = Trace{}) {
   const int p_update = kGen ? s.p_update : 0;
   const int n_fp = kGen ? s.K : 1;  // fixed-point steps per iteration
-  constexpr int VS = pad4(J * I);
+  constexpr int VS = pad4(kEq20Sums<I, J>);
   constexpr bool kOnePass = I * I * I <= 64;       // all I weighted sums in one sweep
   constexpr int VQ = kOnePass ? pad4(I * I * I) : pad4(I * I);
   constexpr int QSTRIDE = kOnePass ? VQ : I * VQ;  // per-wave stride of the Q partials
@@ -143,11 +143,13 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 
     // ---- phase A: E-step statistics, v update, eq. 20 summands ------------
     {
-      float S[J][I];
+      float S0[J], S1[J][I], lamI[J][I];
 #pragma unroll
-      for (int j = 0; j < J; ++j)
+      for (int j = 0; j < J; ++j) {
+        S0[j] = 0.f;
 #pragma unroll
-        for (int i = 0; i < I; ++i) S[j][i] = 0.f;
+        for (int i = 0; i < I; ++i) { S1[j][i] = 0.f; lamI[j][i] = lam[j][i] * (1.0f / float(I)); }
+      }
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         if (wbase + k * T < s.N) {  // wave-uniform: skip slots no lane of the wave owns
@@ -178,21 +180,34 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 #pragma unroll
             for (int i = 0; i < I; ++i) y2k[k][i] = y2[i];
           }
-          as_point_em<I, J>(y2, lam, v[k], S, ok);
+          // a slot every lane of the wave owns skips the per-lane selects
+          if (wbase + k * T + kWave <= s.N)
+            as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, true);
+          else
+            as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, ok);
         }
       }
-      float flat[J * I];
+      float flat[kEq20Sums<I, J>];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        flat[j] = S0[j];
+#pragma unroll
+        for (int i = 0; i < I; ++i) flat[J + j * I + i] = S1[j][i];
+      }
+      wave_totals_to_lds<kEq20Sums<I, J>>(flat, redS, VS);  // slot of wave `wave`
+    }
+    __syncthreads();
+    // eq. 20: lambda (S0_j + lambda S1_ji) / N with the old lambda
+    {
+      float s0[J], s1[J][I];
+      sum_waves<kEq20Sums<I, J>>(binS, VS, nw, [&](int k, float t) {
+        if (k < J) s0[k] = t; else s1[(k - J) / I][(k - J) % I] = t;
+      });
 #pragma unroll
       for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int i = 0; i < I; ++i) flat[j * I + i] = S[j][i];
-      wave_totals_to_lds<J * I>(flat, redS, VS);  // slot of wave `wave`
+        for (int i = 0; i < I; ++i) lam[j][i] = eq20_lambda(lam[j][i], s0[j], s1[j][i], invN);
     }
-    __syncthreads();
-    // eq. 20: old lambda times the scaled sum
-    sum_waves<J * I>(binS, VS, nw, [&](int k, float t) {
-      lam[k / I][k % I] = t * (lam[k / I][k % I] * invN);
-    });
 
     // ---- phase B: the weighted sums N G_i of y y^H (eq. 23) ----------------
     if constexpr (kOnePass) {
@@ -331,7 +346,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       } else {
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] = (a == c) ? fN : 0.f; ai[a] = 0.f; }
-        herm_solve<I>(Sr, Si, ar, ai);
+        if (!herm_solve<I>(Sr, Si, ar, ai) && tb < I) atomicOr(s.flag, kFlagSingular);
       }
       // K > 1: further fixed-point steps a_c = G_c^-1 [A^-H]_c; lane b holds
       // column b of the current A, gathered with readlane (no LDS, no
@@ -352,7 +367,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
         pinvh_col<I, float>(A2r, A2i, c, ar, ai);
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
-        herm_solve<I>(Sr, Si, ar, ai);
+        if (!herm_solve<I>(Sr, Si, ar, ai) && tb < I) atomicOr(s.flag, kFlagSingular);
       }
       // p_c = P_old a_c; P_old is read from LDS again (the copy in registers
       // from phase A is not kept alive through phase B).  Lane c < I writes
@@ -467,6 +482,30 @@ __global__ __launch_bounds__(kResMaxBlock) void k_as_resident_batch(const DevSta
   as_resident_body<I, J, NPT, false, kGen>(s, t.y, nb, n_iter);
 }
 
+// The same with a work queue: a grid of as many workgroups as fit on the
+// device at once, each taking the next tile from a device counter (which
+// the host resets to zero before the launch) until the table is exhausted.
+// Every workgroup leaves once the counter passes the table's end.
+template <int I, int J, int NPT, bool kGen>
+__global__ __launch_bounds__(kResMaxBlock) void k_as_resident_batch_q(const DevState* __restrict__ states,
+                                                                      const int2* __restrict__ tiles, int ntiles,
+                                                                      int n_iter, int* __restrict__ counter) {
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int k = next;
+    __syncthreads();  // every lane has read `next` before lane 0 takes another tile
+    if (k >= ntiles) break;
+    const int2 t = tiles[k];
+    const DevState s = states[t.x];
+    int nb = 1;
+    asm volatile("" : "+s"(nb));
+    as_resident_body<I, J, NPT, false, kGen>(s, t.y, nb, n_iter);
+    __syncthreads();  // the tile's last LDS reads before the next tile's writes
+  }
+}
+
 // Register budget of the resident kernel: NPT points of y (2I), v (J), the
 // eq. 23 weights (I) and, up to I = 4, x (2I) per lane.
 template <int I, int J>
@@ -486,35 +525,66 @@ int as_resident_fits(int N, int waves, int bpw) {
 // Batched launch: tiles of problems whose N are at most n_max, one workgroup
 // of `waves` waves per tile; `general` when any member takes K > 1 or another
 // P update.
+// One tile per workgroup in table order, or (counter != NULL) the work-queue
+// form with as many workgroups as fit on the device.  Where the queue
+// kernel's registers overflow to scratch memory (the tile loop keeps a few
+// more values live than the one-tile kernel, which the largest bodies do not
+// have to spare) the one-tile form is launched instead.  *queued (when not
+// NULL) tells which form ran.
+template <int I, int J, int NPT, bool kGen>
+hipError_t launch_as_batch_npt(const DevState* states, const int2* tiles, int ntiles, hipStream_t st, int n_iter,
+                               int T, int* counter, int* queued) {
+  static const int q_scratch = [] {
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_as_resident_batch_q<I, J, NPT, kGen>)) !=
+        hipSuccess)
+      return 1;
+    return a.localSizeBytes > 0 ? 1 : 0;
+  }();
+  if (queued) *queued = (counter && !q_scratch) ? 1 : 0;
+  if (!counter || q_scratch) {
+    hipLaunchKernelGGL((k_as_resident_batch<I, J, NPT, kGen>), dim3(ntiles), dim3(T), 0, st, states, tiles, n_iter);
+    return hipGetLastError();
+  }
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_as_resident_batch_q<I, J, NPT, kGen>, T, 0);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  long long g = (long long)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  g = g < ntiles ? g : ntiles;
+  if ((e = launch_set_flag(counter, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_as_resident_batch_q<I, J, NPT, kGen>), dim3((unsigned)g), dim3(T), 0, st, states, tiles,
+                     ntiles, n_iter, counter);
+  return hipGetLastError();
+}
+
 template <int I, int J, bool kGen>
 hipError_t launch_as_batch_g(const DevState* states, const int2* tiles, int ntiles, int n_max, hipStream_t st,
-                             int n_iter, int waves) {
+                             int n_iter, int waves, int* counter, int* queued) {
   const int T = waves * kWave;
   const int need = (n_max + T - 1) / T;
   constexpr int mx = res_max_npt<I, J>();
-  dim3 grid(ntiles), block(T);
   if (ntiles <= 0) return hipSuccess;
-  if (need <= 4)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, 4, kGen>), grid, block, 0, st, states, tiles, n_iter);
-  else if (need <= 8 && mx >= 8)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 8 ? 8 : 4), kGen>), grid, block, 0, st, states, tiles,
-                       n_iter);
-  else if (need <= 12 && mx >= 12)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 12 ? 12 : 4), kGen>), grid, block, 0, st, states, tiles,
-                       n_iter);
-  else if (need <= 16 && mx >= 16)
-    hipLaunchKernelGGL((k_as_resident_batch<I, J, (mx >= 16 ? 16 : 4), kGen>), grid, block, 0, st, states, tiles,
-                       n_iter);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (need <= 4) return launch_as_batch_npt<I, J, 4, kGen>(states, tiles, ntiles, st, n_iter, T, counter, queued);
+  if (need <= 8 && mx >= 8)
+    return launch_as_batch_npt<I, J, (mx >= 8 ? 8 : 4), kGen>(states, tiles, ntiles, st, n_iter, T, counter,
+                                                              queued);
+  if (need <= 12 && mx >= 12)
+    return launch_as_batch_npt<I, J, (mx >= 12 ? 12 : 4), kGen>(states, tiles, ntiles, st, n_iter, T, counter,
+                                                                queued);
+  if (need <= 16 && mx >= 16)
+    return launch_as_batch_npt<I, J, (mx >= 16 ? 16 : 4), kGen>(states, tiles, ntiles, st, n_iter, T, counter,
+                                                                queued);
+  return hipErrorInvalidValue;
 }
 
 template <int I, int J>
 hipError_t launch_as_batch_resident(const DevState* states, const int2* tiles, int ntiles, int n_max,
-                                    hipStream_t st, int n_iter, int waves, bool general) {
-  return general ? launch_as_batch_g<I, J, true>(states, tiles, ntiles, n_max, st, n_iter, waves)
-                 : launch_as_batch_g<I, J, false>(states, tiles, ntiles, n_max, st, n_iter, waves);
+                                    hipStream_t st, int n_iter, int waves, bool general, int* counter,
+                                    int* queued) {
+  return general ? launch_as_batch_g<I, J, true>(states, tiles, ntiles, n_max, st, n_iter, waves, counter, queued)
+                 : launch_as_batch_g<I, J, false>(states, tiles, ntiles, n_max, st, n_iter, waves, counter, queued);
 }
 
 template <int I, int J, bool kGen>

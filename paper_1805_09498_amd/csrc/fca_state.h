@@ -20,6 +20,13 @@ constexpr int kResMaxIK = 4;
 // totals into llf.
 constexpr int kLoglikDetInTileMaxI = 4;
 
+// Bits of DevState::flag, read by the host when the "check_finite" option is
+// on (kernels set them with atomicOr; the host clears the flag first).
+constexpr int kFlagNonFinite = 1;      // a NaN or Inf parameter after an update
+constexpr int kFlagSingular = 2;       // a pivot <= 0 in an eq. 23 solve, a per-point C or a per-bin S_j
+constexpr int kFlagNonPositive = 4;    // parameter check: v or lambda not positive and finite
+constexpr int kFlagSingularParam = 8;  // parameter check: P(f) singular, or S_j not positive definite
+
 // Internal layouts (library-owned):
 //   xs   [F][2I][Npad]  split-complex mixture: plane i = Re x_i, plane I+i = Im x_i
 //   vs   [F][J][Npad]   v_j(n,f), frames contiguous
@@ -31,7 +38,8 @@ struct DevState {
   int nchunk;     // tiles per bin of the AS streaming kernels
   int nchunk_em;  // tiles per bin of the EM kernels
   int K;          // fixed-point steps per hybrid iteration
-  int p_update;   // P step: 0 fixed point (eq. 23), 1 gradient, 2 natural gradient
+  int p_update;   // P step: 0 fixed point (eq. 23), 1 gradient, 2 natural gradient, 3 Newton,
+                  // 4 EM with P in the M-step
   float p_step;   // step size of the gradient-type P steps
   const float* xs;
   float* vs;
@@ -41,10 +49,11 @@ struct DevState {
   float2* Rinv;
   float* partA;   // scratch per-tile partial sums
   float* partB;
+  float* partE;   // EM with P in the M-step: per-tile sums [F][nchunk][J][I*I + I]
   double* partL;  // [F][max(nchunk, nchunk_em)]
   double* llf;    // [F]
   double* ll;     // [1]
-  int* flag;      // [1]
+  int* flag;      // [1] kFlag* bits
 };
 
 // Arguments of the adjoint kernels: the state before (t) and after (n) one
@@ -86,7 +95,9 @@ struct KernelSet {
   hipError_t (*as_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves, int bpw);
   int (*as_resident_fits)(int N, int waves, int bpw);
   hipError_t (*as_batch_resident)(const DevState* states, const int2* tiles, int ntiles, int n_max,
-                                  hipStream_t, int n_iter, int waves, bool general);
+                                  hipStream_t, int n_iter, int waves, bool general,
+                                  int* queue_counter,  // NULL: one workgroup per tile
+                                  int* queued);        // out (may be NULL): 1 if the queue form ran
   hipError_t (*em_iter)(const DevState&, hipStream_t);
   hipError_t (*em_iter_resident)(const DevState&, hipStream_t, int n_iter, int waves);
   int (*em_resident_fits)(int N, int waves);
@@ -100,6 +111,7 @@ struct KernelSet {
                                        const Trace&);
   hipError_t (*adj_iter)(const DevState&, const AdjIter&, hipStream_t);
   hipError_t (*adj_wiener)(const DevState&, const float2* gout, const AdjIter&, hipStream_t);
+  hipError_t (*check_matrices)(const DevState&, hipStream_t, int em);  // P(f) / S_j(f), kFlagSingularParam
 };
 
 // Non-templated kernels' launchers (fca_common.hip).
@@ -108,6 +120,12 @@ hipError_t launch_pack_v(const float* v, float* vs, int F, int N, int J, int Npa
 hipError_t launch_unpack_v(const float* vs, float* v, int F, int N, int J, int Npad, hipStream_t st);
 hipError_t launch_unpack_x(const float* xs, float2* x, int F, int N, int I, int Npad, hipStream_t st);
 hipError_t launch_check_finite(const float* a, long long n, int* flag, hipStream_t st);
+// v [F][J][Npad] (frames n < N) and lam (n_lam floats, may be NULL) positive
+// and finite, else kFlagNonPositive.
+hipError_t launch_check_positive(const float* vs, int F, int J, int N, int Npad, const float* lam, long long n_lam,
+                                 int* flag, hipStream_t st);
+// *flag = value, by a kernel (no memset node when a caller captures the stream).
+hipError_t launch_set_flag(int* flag, int value, hipStream_t st);
 hipError_t launch_sum_f(const double* llf, int F, double* out, hipStream_t st);
 hipError_t launch_sum_chunks(const double* part, int F, int nchunk, double* out, hipStream_t st);
 

@@ -31,6 +31,7 @@ FCA_ERR_UNSUPPORTED = -2
 FCA_ERR_HIP = -3
 FCA_ERR_STATE = -4
 FCA_ERR_NONFINITE = -5
+FCA_ERR_SINGULAR = -6
 
 FCA_METHOD_AS = 0
 FCA_METHOD_EM = 1

@@ -64,60 +64,87 @@ def _solve_bound(G, a, epsG, I):
     return out, kap
 
 
-def as_point_stats(x, v, lam, P):
-    """Per-point quantities of the E-step and the v update, with their
-    first-order absolute error bounds (the FP32 evaluation from exact
-    inputs).  Returns a dict of arrays."""
+def as_point_stats(x, v, lam, P, dv_in=0.0, dlam_in=0.0, dP_in=0.0):
+    """Per-point quantities of the E-step and the v update, with first-order
+    absolute error bounds of their FP32 evaluation from inputs (v, lam, P)
+    that carry absolute errors dv_in, dlam_in, dP_in (0: exact inputs).
+    Returns a dict of arrays."""
     x = np.asarray(x, np.complex128)
     v = np.asarray(v, np.float64)
     lam = np.asarray(lam, np.float64)
     P = np.asarray(P, np.complex128)
     I = x.shape[2]
     J = v.shape[2]
+    dv_in = np.broadcast_to(np.asarray(dv_in, np.float64), v.shape)
+    dlam_in = np.broadcast_to(np.asarray(dlam_in, np.float64), lam.shape)
+    dP_in = np.broadcast_to(np.asarray(dP_in, np.float64), P.shape)
+    ax = np.abs(x)
     y = np.einsum("fki,fnk->fni", np.conj(P), x)
     ay = np.abs(y)
-    dy = gamma(4 * I) * np.einsum("fki,fnk->fni", np.abs(P), np.abs(x))       # |delta y_i|
+    dy = gamma(4 * I) * np.einsum("fki,fnk->fni", np.abs(P), ax) + np.einsum("fki,fnk->fni", dP_in, ax)
     q = ay ** 2
     dq = 2.0 * ay * dy + dy ** 2 + gamma(3) * q
     d = np.einsum("fnj,fji->fni", v, lam)
-    dd = gamma(J + 1) * d
+    dd = gamma(J + 1) * d + np.einsum("fnj,fji->fni", dv_in, lam) + np.einsum("fnj,fji->fni", v, dlam_in)
     # 1/d by the hardware reciprocal: relative error of d plus two roundings
-    drcp = gamma(J + 3)
+    rel_d = dd / d + gamma(2)
     h = q / d - 1.0
-    dh = dq / d + q / d * drcp + gamma(1) * (q / d + 1.0)
+    dh = dq / d + q / d * rel_d + gamma(1) * (q / d + 1.0)
     e = h / d
-    de = dh / d + np.abs(h) / d * drcp + gamma(1) * np.abs(e)
+    de = dh / d + np.abs(h) / d * rel_d + gamma(1) * np.abs(e)
     W = 1.0 + np.einsum("fnj,fji,fni->fnj", v, lam, e) / I
     MW = 1.0 + np.einsum("fnj,fji,fni->fnj", v, lam, np.abs(e)) / I
-    dW = np.einsum("fnj,fji,fni->fnj", v, lam, de) / I + gamma(I + 6) * MW
+    dW = (np.einsum("fnj,fji,fni->fnj", v, lam, de) + np.einsum("fnj,fji,fni->fnj", dv_in, lam, np.abs(e))
+          + np.einsum("fnj,fji,fni->fnj", v, dlam_in, np.abs(e))) / I + gamma(I + 6) * MW
     v_new = v * W
-    dv = v * dW + gamma(1) * np.abs(v_new)
+    dv = v * dW + dv_in * np.abs(W) + gamma(1) * np.abs(v_new)
     vl = v[:, :, :, None] * lam[:, None, :, :]                                # [F][N][J][I]
+    dvl = dv_in[:, :, :, None] * lam[:, None, :, :] + v[:, :, :, None] * dlam_in[:, None, :, :]
     r = 1.0 + vl * e[:, :, None, :]
     Mr = 1.0 + vl * np.abs(e)[:, :, None, :]
-    dr = vl * de[:, :, None, :] + gamma(3) * Mr
-    return dict(y=y, ay=ay, dy=dy, q=q, dq=dq, d=d, dd=dd, W=W, dW=dW, v_new=v_new, dv=dv, r=r, dr=dr)
+    dr = vl * de[:, :, None, :] + dvl * np.abs(e)[:, :, None, :] + gamma(3) * Mr
+    return dict(y=y, ay=ay, dy=dy, q=q, dq=dq, d=d, dd=dd, e=e, de=de, W=W, dW=dW, v_new=v_new, dv=dv, r=r,
+                dr=dr)
 
 
-def as_em_bounds(x, v, lam, P):
+def as_em_bounds(x, v, lam, P, dv_in=0.0, dlam_in=0.0, dP_in=0.0):
     """Bounds of the EM half-step (eq. 16-20): returns (dv [F][N][J],
-    dlam [F][J][I], stats) for the FP32 evaluation from exact inputs."""
-    st = as_point_stats(x, v, lam, P)
+    dlam [F][J][I], stats) for the FP32 evaluation from inputs carrying the
+    given absolute errors.  The kernels sum eq. 20 in two parts per bin,
+    S0_j = sum_n 1/W_j and S1_ji = sum_n (v_j/W_j) e_i, and form
+    lambda' = lambda (S0 + lambda S1) / N."""
+    st = as_point_stats(x, v, lam, P, dv_in, dlam_in, dP_in)
+    v = np.asarray(v, np.float64)
     lam = np.asarray(lam, np.float64)
+    dv_in = np.broadcast_to(np.asarray(dv_in, np.float64), v.shape)
+    dlam_in = np.broadcast_to(np.asarray(dlam_in, np.float64), lam.shape)
     N = st["y"].shape[1]
-    W = st["W"][..., None]
-    t = lam[:, None, :, :] * st["r"] / W
-    dt = lam[:, None, :, :] * (st["dr"] / W + np.abs(st["r"]) * st["dW"][..., None] / W ** 2) + gamma(4) * np.abs(t)
-    dlam = dt.mean(axis=1) + gamma(_levels(N) + 3) * np.abs(t).mean(axis=1)
+    L = _levels(N)
+    W = st["W"]
+    rW = 1.0 / W
+    drW = np.abs(rW) * (st["dW"] / np.abs(W) + gamma(2))
+    m = v * rW
+    dm = v * drW + dv_in * np.abs(rW) + gamma(1) * np.abs(m)
+    e, de = st["e"], st["de"]
+    me = m[..., None] * e[:, :, None, :]                                       # [F][N][J][I]
+    dme = np.abs(m)[..., None] * de[:, :, None, :] + dm[..., None] * np.abs(e)[:, :, None, :] + gamma(1) * np.abs(me)
+    S0 = rW.sum(axis=1)                                                       # [F][J]
+    dS0 = drW.sum(axis=1) + gamma(L) * np.abs(rW).sum(axis=1)
+    S1 = me.sum(axis=1)                                                       # [F][J][I]
+    dS1 = dme.sum(axis=1) + gamma(L) * np.abs(me).sum(axis=1)
+    dlam = (lam / N) * (dS0[..., None] + lam * dS1) + (dlam_in / N) * np.abs(S0[..., None] + 2.0 * lam * S1) \
+        + gamma(3) * (lam / N) * (S0[..., None] + lam * np.abs(S1))
     return st["dv"], dlam, st
 
 
-def as_step_bounds(x, v, lam, P, K=1, p_update=0, mu=0.1):
+def as_step_bounds(x, v, lam, P, K=1, p_update=0, mu=0.1, dv_in=0.0, dlam_in=0.0, dP_in=0.0):
     """First-order absolute error bounds of one hybrid iteration (Section 4.3)
-    evaluated in FP32 from the exact state (v, lam, P):
-    returns dict(v=[F][N][J], lam=[F][J][I], P=[F][I][I], kappa=[F][I]),
-    kappa being the condition numbers of the eq. 23 matrices in the basis of
-    y (G_c = P^H Q_c P), whose solves dominate the bound on P.
+    evaluated in FP32 from the state (v, lam, P), which may carry absolute
+    errors dv_in, dlam_in, dP_in from earlier iterations (0: exact):
+    returns dict(v=[F][N][J], lam=[F][J][I], P=[F][I][I], kappa=[F][I],
+    epsG=[F][I]), kappa being the condition numbers of the eq. 23 matrices
+    in the basis of y (G_c = P^H Q_c P), whose solves dominate the bound on
+    P, and epsG the relative error of those matrices.
 
     p_update 0: K fixed-point steps (eq. 23); 1: gradient step P + mu g;
     2: natural-gradient step P + mu P P^H g, with g = (1/N) dL2/dP* (eq. 21).
@@ -125,7 +152,8 @@ def as_step_bounds(x, v, lam, P, K=1, p_update=0, mu=0.1):
     x = np.asarray(x, np.complex128)
     P = np.asarray(P, np.complex128)
     F, N, I = x.shape
-    dv, dlam, st = as_em_bounds(x, v, lam, P)
+    dP_in = np.broadcast_to(np.asarray(dP_in, np.float64), P.shape)
+    dv, dlam, st = as_em_bounds(x, v, lam, P, dv_in, dlam_in, dP_in)
     v_new, lam_new = oracle.as_em_half_step(x, v, lam, P)
     J = v_new.shape[2]
     y, ay, dy = st["y"], st["ay"], st["dy"]
@@ -161,7 +189,9 @@ def as_step_bounds(x, v, lam, P, K=1, p_update=0, mu=0.1):
                 An[:, :, c] = a
                 dAn[:, c] = da + Ginv_norm * dB[:, c]
             A, dA = An, dAn
-        dP = np.einsum("fkl->fk", absP)[:, :, None] * dA[:, None, :] + gamma(2 * I + 2) * np.einsum("fkl,flc->fkc", absP, np.abs(A))
+        dP = (np.einsum("fkl->fk", absP)[:, :, None] * dA[:, None, :]
+              + gamma(2 * I + 2) * np.einsum("fkl,flc->fkc", absP, np.abs(A))
+              + np.einsum("fkl,flc->fkc", dP_in, np.abs(A)))
     else:
         # Gamma's column c is G_c e_c; natural: A = 1 + mu (1 - Gamma), P A;
         # gradient: P + mu P^-H (1 - Gamma).
@@ -170,7 +200,9 @@ def as_step_bounds(x, v, lam, P, K=1, p_update=0, mu=0.1):
         if p_update == 2:
             A = eye + mu * (eye - Gam)
             dA = mu * dGam + gamma(3) * (1.0 + mu * (1.0 + np.linalg.norm(Gam, axis=1)))
-            dP = np.einsum("fkl->fk", absP)[:, :, None] * dA[:, None, :] + gamma(2 * I + 2) * np.einsum("fkl,flc->fkc", absP, np.abs(A))
+            dP = (np.einsum("fkl->fk", absP)[:, :, None] * dA[:, None, :]
+                  + gamma(2 * I + 2) * np.einsum("fkl,flc->fkc", absP, np.abs(A))
+                  + np.einsum("fkl,flc->fkc", dP_in, np.abs(A)))
         else:
             Pinv = np.linalg.inv(P)
             B = _herm(Pinv)
@@ -179,9 +211,11 @@ def as_step_bounds(x, v, lam, P, K=1, p_update=0, mu=0.1):
             M = eye - Gam
             g = np.einsum("fab,fbc->fac", B, M)
             dM = dGam + gamma(2)
-            dg = nPinv[:, None] * dM + (I * gamma(3 * I + 1) * kP * nPinv)[:, None] * np.linalg.norm(M, axis=1) \
-                + gamma(2 * I + 2) * np.linalg.norm(np.einsum("fab,fbc->fac", np.abs(B), np.abs(M)), axis=1)
-            dP = mu * dg[:, None, :] + gamma(2) * (absP + mu * np.abs(g))
+            nMcol = np.linalg.norm(M, axis=1)
+            dg = nPinv[:, None] * dM + (I * gamma(3 * I + 1) * kP * nPinv)[:, None] * nMcol \
+                + gamma(2 * I + 2) * np.linalg.norm(np.einsum("fab,fbc->fac", np.abs(B), np.abs(M)), axis=1) \
+                + (nPinv ** 2 * np.linalg.norm(dP_in, axis=(-2, -1)))[:, None] * nMcol
+            dP = mu * dg[:, None, :] + gamma(2) * (absP + mu * np.abs(g)) + dP_in
     return dict(v=dv, lam=dlam, P=dP, kappa=kap, epsG=epsG)
 
 
@@ -276,3 +310,77 @@ def loglik_bin_bounds(x, v, lam, P):
     kP = np.linalg.cond(P)
     dlogdet = I * I * gamma(3 * I + 1) * kP
     return point.sum(axis=(1, 2)) + 2.0 * N * dlogdet + gamma(4) * N * I * math.log(math.pi)
+
+
+def as_variant_p_bounds(x, v, lam, P, p_update, dv_in=0.0, dlam_in=0.0, dP_in=0.0):
+    """Bounds on P after one hybrid iteration whose P update is Newton's
+    step (p_update 3) or EM with P in the M-step (p_update 4), norm-wise per
+    bin and broadcast to every entry of the bin's P [F][I][I].
+
+    Both updates are P_new = P (1 + X) or P A with per-bin small solves:
+    * Newton: the reduced (2I^2 - I)-square real system M s = -g (the
+      oracle's as_newton_system at the new v, lambda), whose entries carry
+      the relative error eps_G of the eq. 23 sums; Gaussian elimination
+      adds n gamma(3n) (backward error), both amplified by cond(M);
+    * EM with P: each column solves H_i a = A^-H e_i (cond(H_i), and
+      cond(A) for A^-H), H_i carrying the error of sums like eps_G plus
+      J I roundings per term; the columns are swept in order, so an error
+      in earlier columns reaches later ones through A^-H (factor
+      1 + cond(A)).
+    """
+    x = np.asarray(x, np.complex128)
+    P = np.asarray(P, np.complex128)
+    F, N, I = x.shape
+    base = as_step_bounds(x, v, lam, P, dv_in=dv_in, dlam_in=dlam_in, dP_in=dP_in)
+    epsG = np.max(base["epsG"], axis=1)                                      # [F]
+    nPin = np.linalg.norm(np.broadcast_to(np.asarray(dP_in, np.float64), P.shape), axis=(-2, -1))
+    v_new, lam_new = oracle.as_em_half_step(x, v, lam, P)
+    J = v_new.shape[2]
+    nP = np.linalg.norm(P, ord=2, axis=(-2, -1))
+    if p_update == 3:
+        n = 2 * I * I - I
+        bound = np.empty(F)
+        for f, (H, g) in enumerate(oracle.as_newton_system(x, v_new, lam_new, P)):
+            s = np.linalg.solve(H, -g)
+            kM = np.linalg.cond(H)
+            dX = kM * (epsG[f] + n * gamma(3 * n)) * (np.linalg.norm(s) + 1.0)
+            bound[f] = nP[f] * dX + (gamma(2 * I + 2) * nP[f] + nPin[f]) * (1.0 + np.linalg.norm(s))
+    else:
+        mu, Phi = oracle.fca_estep(x, np.asarray(v, np.float64), oracle.as_spatial_cov(P, lam))
+        M = np.einsum("fnja,fnjb->fnjab", mu, np.conj(mu)) + Phi
+        V = np.einsum("fnjab,fnj,fji->fiab", M, 1.0 / v_new, 1.0 / lam_new) / (N * J)
+        H = np.einsum("fka,fikl,flb->fiab", np.conj(P), V, P)                  # P^H V_i P
+        P_new = oracle.as_em_p_step(x, v, lam, P)[2]
+        A = np.linalg.solve(P, P_new)
+        kA = np.linalg.cond(A)
+        kH = np.linalg.cond(H)                                                # [F][I]
+        na = np.linalg.norm(A, axis=1)                                        # column norms [F][I]
+        epsH = epsG + gamma(J * I + 8)
+        per_col = na * (kH * (epsH[:, None] + I * gamma(3 * I + 1)) + (kA * I * gamma(3 * I + 1))[:, None]
+                        + gamma(2 * I + 4))
+        dA = (1.0 + kA) * per_col.sum(axis=1)
+        bound = nP * dA + (gamma(2 * I + 2) * nP + nPin) * np.linalg.norm(A, ord=2, axis=(-2, -1))
+    return np.broadcast_to(bound[:, None, None], P.shape).copy()
+
+
+def loglik_bin_sensitivity(x, v, lam, P):
+    """First-order size of the change of each bin's L2 (eq. 14) [F] per unit
+    relative error of the state: a relative error e of d_i moves each term
+    -ln d_i - |y_i|^2 / d_i by at most e (1 + |y_i|^2 / d_i); one of P moves
+    |y_i|^2 by 2 e |y_i|^2 and ln|det P| by I cond(P) e."""
+    x = np.asarray(x, np.complex128)
+    P = np.asarray(P, np.complex128)
+    F, N, I = x.shape
+    st = as_point_stats(x, v, lam, P)
+    q_d = st["q"] / st["d"]
+    return (1.0 + 3.0 * q_d).sum(axis=(1, 2)) + 2.0 * N * I * np.linalg.cond(P)
+
+
+def em_loglik_bin_sensitivity(x, v, S):
+    """The same for L1 (eq. 5) of FCA: a relative error e of the model
+    covariance C = sum_j v_j S_j moves -ln det C - x^H C^-1 x by at most
+    cond(C) e (I + x^H C^-1 x)."""
+    x = np.asarray(x, np.complex128)
+    C = np.einsum("fnj,fjab->fnab", np.asarray(v, np.float64), np.asarray(S, np.complex128))
+    quad = np.real(np.einsum("fna,fna->fn", np.conj(x), np.linalg.solve(C, x[..., None])[..., 0]))
+    return (np.linalg.cond(C) * (C.shape[-1] + quad)).sum(axis=1)

@@ -36,14 +36,19 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
-def per_bin_rel(a, b, axis=0):
-    """The largest relative Frobenius error over the bins (axis `axis`)."""
+def _bin_errors(a, b, axis=0):
+    """Relative Frobenius error of every bin (axis `axis`)."""
     a = np.moveaxis(np.asarray(a), axis, 0)
     b = np.moveaxis(np.asarray(b), axis, 0)
     F = b.shape[0]
     num = np.linalg.norm((a - b).reshape(F, -1), axis=1)
     den = np.linalg.norm(b.reshape(F, -1), axis=1)
-    return float(np.max(num / np.where(den > 0, den, 1.0)))
+    return num / np.where(den > 0, den, 1.0)
+
+
+def per_bin_rel(a, b, axis=0):
+    """The largest relative Frobenius error over the bins (axis `axis`)."""
+    return float(np.max(_bin_errors(a, b, axis)))
 
 
 def elem_rel(a, b, axis=0, floor=ELEM_FLOOR):
@@ -86,7 +91,13 @@ def check(name, got, ref, bound=None, tol=None, axis=0, bin_tol=None):
     if tol is not None:
         assert m["rel"] <= tol, f"{name}: relative error above {tol} {m}"
     if bin_tol is not None:
-        assert m["bin_rel"] <= bin_tol, f"{name}: a bin's relative error above {bin_tol} {m}"
+        bins = _bin_errors(got, ref, axis)
+        bt = np.broadcast_to(np.asarray(bin_tol, np.float64), bins.shape)
+        m["bin_rel_over_tol"] = float(np.max(bins / bt))
+        if log:
+            with open(log, "a") as fh:
+                fh.write(json.dumps(dict(m, name=m["name"] + " [bins]")) + "\n")
+        assert np.all(bins <= bt), f"{name}: a bin's relative error above its bound {m}"
     return m
 
 
@@ -133,45 +144,106 @@ def oracle_as(p, n_iter, K=1):
     return v, lam, P
 
 
-def oracle_as_bounded(p, n_iter, K=1, p_update=0, mu=0.1):
+def _bin_rel(bound, ref):
+    """Per-bin relative Frobenius size of an absolute bound (axis 0 = bin)."""
+    F = ref.shape[0]
+    num = np.linalg.norm(np.asarray(bound).reshape(F, -1), axis=1)
+    den = np.linalg.norm(np.asarray(ref).reshape(F, -1), axis=1)
+    return num / np.where(den > 0, den, 1.0)
+
+
+def oracle_as_bounded(p, n_iter, K=1, p_update=0, mu=0.1, rho_every=1):
     """The oracle's (v, lam, P) after n_iter iterations from the problem's
-    start, with first-order bounds on the error of an FP32 run: the bound of
-    each iteration's own rounding, evaluated at the oracle's state before
-    it, summed over the iterations (an error carried into the next
-    iteration is taken not to grow; the comparisons check exactly that).
+    start, with the bounds an FP32 run is checked against:
+
+    * n_iter = 1: per-entry first-order bounds of the iteration's rounding
+      (tests/error_bounds.py), in b["v"], b["lam"], b["P"];
+    * always, per-bin relative bounds b["bin_rel"] [F]: the sum over the
+      iterations of rho_m(f), the largest per-bin relative size of iteration
+      m's own first-order bound (of v, lambda or P, evaluated at the
+      oracle's state before that iteration).  This takes a relative error
+      carried into an iteration not to grow (the iteration map treated as
+      non-expansive; worst-case propagation through the eq. 23 solves
+      multiplies by their condition numbers every iteration and bounds
+      nothing after two); the comparisons check that assumption.  With
+      rho_every = k the bound is evaluated every k-th iteration and counted
+      k times.
+
     Returns (v, lam, P, bounds dict, largest eq. 23 condition number)."""
     from tests import error_bounds as EB
     v, lam, P = p.v0, p.lam0, p.P0
-    acc = None
     kmax = 1.0
-    for _ in range(n_iter):
-        b = EB.as_step_bounds(p.x, v, lam, P, K=K, p_update=p_update, mu=mu)
-        kmax = max(kmax, float(np.max(b["kappa"])))
-        acc = b if acc is None else {k: acc[k] + b[k] for k in ("v", "lam", "P")}
+    first = None
+    rho = np.zeros(p.x.shape[0])
+    for m in range(n_iter):
+        if m % rho_every == 0:
+            b = EB.as_step_bounds(p.x, v, lam, P, K=K, p_update=p_update if p_update < 3 else 0, mu=mu)
+            if p_update >= 3:
+                b = dict(b, P=EB.as_variant_p_bounds(p.x, v, lam, P, p_update))
+            kmax = max(kmax, float(np.max(b["kappa"])))
+            if first is None:
+                first = b
         if p_update == 0:
-            v, lam, P = oracle.fastfca_as_step(p.x, v, lam, P, K=K)
+            vn, ln, Pn = oracle.fastfca_as_step(p.x, v, lam, P, K=K)
+        elif p_update == 3:
+            vn, ln, Pn = oracle.fastfca_as_step_newton(p.x, v, lam, P)
+        elif p_update == 4:
+            vn, ln, Pn = oracle.as_em_p_step(p.x, v, lam, P)
         else:
-            v, lam, P = oracle.fastfca_as_step_grad(p.x, v, lam, P, mu, natural=(p_update == 2))
-    return v, lam, P, acc, kmax
+            vn, ln, Pn = oracle.fastfca_as_step_grad(p.x, v, lam, P, mu, natural=(p_update == 2))
+        if m % rho_every == 0:
+            rho += rho_every * np.max(np.stack([_bin_rel(b["v"], vn), _bin_rel(b["lam"], ln),
+                                                _bin_rel(b["P"], Pn)]), axis=0)
+        v, lam, P = vn, ln, Pn
+    bounds = {k: first[k] for k in ("v", "lam", "P")} if n_iter == 1 else {}
+    bounds["bin_rel"] = rho
+    return v, lam, P, bounds, kmax
 
 
-def check_as_params(got, ref_and_bounds, tol=TOL_PARAM, tag=""):
-    """v, lambda, P of a FastFCA-AS run against oracle_as_bounded's result."""
+def check_as_params(got, ref_and_bounds, tol=TOL_PARAM, tag="", tol_P="same"):
+    """v, lambda, P of a FastFCA-AS run against oracle_as_bounded's result:
+    per entry after one iteration, per bin after several; the per-tensor
+    tolerance `tol` when given (`tol_P` for P, by default the same)."""
     v, lam, P = got
     v_ref, lam_ref, P_ref, b, _ = ref_and_bounds
-    check("v" + tag, v, v_ref, b["v"], tol)
-    check("lam" + tag, lam, lam_ref, b["lam"], tol)
-    check("P" + tag, P, P_ref, b["P"], tol)
+    for name, g, r in (("v", v, v_ref), ("lam", lam, lam_ref), ("P", P, P_ref)):
+        t = tol if (name != "P" or tol_P == "same") else tol_P
+        if name in b:
+            check(name + tag, g, r, b[name], t)
+        else:
+            check(name + tag, g, r, tol=t, bin_tol=b["bin_rel"])
 
 
-def check_loglik_bins(Lb, Lb_ref, tol=TOL_LOGLIK, tag=""):
-    """Per-bin log-likelihoods within tol relative to each bin's value (with
-    a floor of 1e-3 of the mean magnitude for bins whose sum nearly
-    cancels)."""
-    Lb = np.asarray(Lb, np.float64)
-    Lb_ref = np.asarray(Lb_ref, np.float64)
-    scale = np.maximum(np.abs(Lb_ref), 1e-3 * np.mean(np.abs(Lb_ref)))
-    return check("loglik_bins" + tag, Lb, Lb_ref, tol * scale)
+def check_loglik_bins(Lb, Lb_ref, bound, tag=""):
+    """Per-bin log-likelihoods within an absolute bound per bin."""
+    return check("loglik_bins" + tag, np.asarray(Lb, np.float64), np.asarray(Lb_ref, np.float64), bound)
+
+
+def as_loglik_bin_bound(p, ref_and_bounds):
+    """Bound of the per-bin L2 of an FP32 run after the iterations that
+    oracle_as_bounded followed: the accumulated per-bin relative state bound
+    times the log-likelihood's sensitivity, plus the evaluation's own
+    rounding at the final state."""
+    from tests import error_bounds as EB
+    v, lam, P, b, _ = ref_and_bounds
+    return b["bin_rel"] * EB.loglik_bin_sensitivity(p.x, v, lam, P) + EB.loglik_bin_bounds(p.x, v, lam, P)
+
+
+def oracle_em_bounded(p, S0, n_iter):
+    """The FCA EM analogue of oracle_as_bounded: the oracle's (v, S) after
+    n_iter iterations, the per-entry bounds of the first iteration and the
+    accumulated per-bin relative bound rho [F]."""
+    from tests import error_bounds as EB
+    v, S = p.v0, S0
+    first = None
+    rho = np.zeros(p.x.shape[0])
+    for _ in range(n_iter):
+        b = EB.em_step_bounds(p.x, v, S)
+        first = b if first is None else first
+        vn, Sn = oracle.fca_em_step(p.x, v, S)
+        rho += np.maximum(_bin_rel(b["v"], vn), _bin_rel(b["S"], Sn))
+        v, S = vn, Sn
+    return v, S, first, rho
 
 
 def oracle_em(p, R, n_iter):

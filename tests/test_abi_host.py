@@ -155,3 +155,13 @@ def test_stft_rejects_bad_frames_on_the_host(lib, W, H):
     lib.fca_istft.argtypes = [vp, i, i, i, i, i, i, vp, vp]
     assert lib.fca_istft(FAKE, 2, 2, 3, W, H, 1000, FAKE, None) == -1
 
+
+def test_status_codes_of_header_and_binding_agree():
+    """Every fca_status of the header, with its value, is a constant of the
+    Python binding (FCA_ERR_SINGULAR included)."""
+    text = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(FCA_(?:OK|ERR_[A-Z]+))\s*=\s*(-?\d+)", text))
+    assert codes["FCA_ERR_SINGULAR"] == -6 and len(codes) == 7
+    from paper_1805_09498_amd import fastfca
+    for k, v in codes.items():
+        assert getattr(fastfca, k) == v, k

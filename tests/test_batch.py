@@ -78,6 +78,30 @@ def test_graph_and_direct_launches_agree_bitwise(ff):
             np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("graph", [1, 0])
+def test_work_queue_equals_one_workgroup_per_tile_bitwise(ff, graph):
+    """The persistent work-queue launch (option "queue") gives the bits of
+    the one-workgroup-per-tile launch: same tiles, same workgroup body; the
+    device counter is reset before every launch (4 + 2 iterations in two
+    calls, replayed graphs included)."""
+    probs = uneven_batch(7, 6, seed=12)
+    out = []
+    for queue in (0, 1):
+        b, _ = batch_of(ff, probs, graph=graph)
+        ff.fca_batch_set_option(b, "autotune", 0)
+        ff.fca_batch_set_option(b, "queue", queue)
+        assert ff.fca_batch_get_option(b, "queue") == queue
+        ff.fca_batch_iterate(b, 4)
+        ff.fca_batch_iterate(b, 2)
+        queued = [ff.fca_batch_get_option(b, "group_queued", g) for g in range(ff.fca_batch_get_option(b, "groups"))]
+        # groups whose queue kernel would need scratch memory keep the first form
+        assert (max(queued) == 1) if queue else (max(queued) == 0), queued
+        out.append([params(ff, ff.fca_batch_context(b, m)) for m in range(len(probs))])
+    for ma, mb in zip(*out):
+        for x, y in zip(ma, mb):
+            np.testing.assert_array_equal(x, y)
+
+
 def test_split_iterations_equal_one_call_bitwise(ff):
     """3 + 3 batch iterations (two graph replays) equal 6 in one call: the
     state written back between launches is the state kept in registers."""
@@ -113,7 +137,7 @@ def test_full_size_uneven_batch_sampled(ff):
 def test_batch_options_and_errors(ff):
     probs = uneven_batch(2, 3, seed=11)
     b, _ = batch_of(ff, probs)
-    for key, val in [("graph", 2), ("waves", 3), ("K", 0), ("nope", 1)]:
+    for key, val in [("graph", 2), ("queue", 2), ("waves", 3), ("K", 0), ("nope", 1)]:
         with pytest.raises(ff.FcaError):
             ff.fca_batch_set_option(b, key, val)
     with pytest.raises(ff.FcaError):

@@ -11,8 +11,9 @@ import pytest
 
 import oracle
 from tests import error_bounds as EB
-from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, check, check_as_params, check_loglik_bins,
-                              oracle_as_bounded, params, problem, rel, run_as, sub_problem, to_dev)
+from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, as_loglik_bin_bound, check, check_as_params,
+                              check_loglik_bins, oracle_as_bounded, params, problem, rel, run_as, sub_problem,
+                              to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,15 +49,13 @@ def test_loglik_after_iterations(ff, cfg, n_iter, path):
     ctx = run_as(ff, p, n_iter, path=path)
     L = ff.fca_loglik(ctx)
     Lb = ff.fca_loglik_bins(ctx).cpu().numpy()
-    v_ref, lam_ref, P_ref = p.v0, p.lam0, p.P0
-    for _ in range(n_iter):
-        v_ref, lam_ref, P_ref = oracle.fastfca_as_step(p.x, v_ref, lam_ref, P_ref)
-    Lb_ref = oracle.loglik_as(p.x, v_ref, lam_ref, P_ref, per_bin=True)
+    ref = oracle_as_bounded(p, n_iter, rho_every=2)
+    Lb_ref = oracle.loglik_as(p.x, *ref[:3], per_bin=True)
     L_ref = float(Lb_ref.sum())
     print(cfg, path, L, L_ref, abs(L - L_ref) / abs(L_ref))
     assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
     assert abs(Lb.sum() - L) <= 1e-9 * abs(L)
-    check_loglik_bins(Lb, Lb_ref, tag=f" {cfg['F']}x{cfg['N']} {n_iter} iterations path {path}")
+    check_loglik_bins(Lb, Lb_ref, as_loglik_bin_bound(p, ref), tag=f" {cfg['F']}x{cfg['N']} {n_iter} iterations path {path}")
 
 
 def test_loglik_headline_run(ff):
@@ -66,14 +65,12 @@ def test_loglik_headline_run(ff):
     ctx = run_as(ff, p, 100)
     L = ff.fca_loglik(ctx)
     Lb = ff.fca_loglik_bins(ctx).cpu().numpy()
-    v, lam, P = p.v0, p.lam0, p.P0
-    for _ in range(100):
-        v, lam, P = oracle.fastfca_as_step(p.x, v, lam, P)
-    Lb_ref = oracle.loglik_as(p.x, v, lam, P, per_bin=True)
+    ref = oracle_as_bounded(p, 100, rho_every=10)
+    Lb_ref = oracle.loglik_as(p.x, *ref[:3], per_bin=True)
     L_ref = float(Lb_ref.sum())
     print("100 iterations", L, L_ref, abs(L - L_ref) / abs(L_ref))
     assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
-    check_loglik_bins(Lb, Lb_ref, tag=" speech10s 100 iterations")
+    check_loglik_bins(Lb, Lb_ref, as_loglik_bin_bound(p, ref), tag=" speech10s 100 iterations")
 
 
 def test_loglik_at_initial_point(ff):

@@ -56,7 +56,7 @@ def test_em_edge_shapes(ff, I, J, F, N):
         check(f"em S edge I{I} J{J} F{F} N{N} path {path}", R, R_ref, b["S"], TOL_PARAM)
 
 
-@pytest.mark.parametrize("I,J,F,N", [(1, 2, 4, 7), (2, 3, 7, 65), (8, 9, 2, 700), (6, 7, 3, 2049)])
+@pytest.mark.parametrize("I,J,F,N", [(1, 2, 4, 7), (2, 3, 7, 65), (8, 9, 2, 700), (8, 6, 3, 333), (6, 7, 3, 2049)])
 def test_loglik_and_wiener_edge(ff, I, J, F, N):
     p = problem(I, J, F, N, seed=7 * I + J)
     ctx = run_as(ff, p, 2)
@@ -164,3 +164,78 @@ def test_nonfinite_input_detected(ff):
     with pytest.raises(ff.FcaError) as e:
         ff.fastfca_as_iterate(ctx, 1)
     assert e.value.status == ff.FCA_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("case", ["lambda_zero", "v_negative", "v_nan", "P_zero_column"])
+def test_parameter_check_on_the_device(ff, case):
+    """With "check_finite", the first iterate call after fca_init (or
+    fca_set_params) checks the parameters the model requires on the device
+    (host-forced invalid values; every kernel runs to completion):
+    non-positive or non-finite v / lambda give FCA_ERR_ARG, a singular P(f)
+    FCA_ERR_SINGULAR, and nothing is iterated.  Valid parameters set
+    afterwards pass."""
+    p = problem(3, 3, 6, 80, seed=3)
+    good = to_dev(p)
+    if case == "lambda_zero":
+        p.lam0[2, 1, 0] = 0.0
+    elif case == "v_negative":
+        p.v0[4, 7, 2] = -1.0
+    elif case == "v_nan":
+        p.v0[1, 79, 0] = np.nan
+    else:
+        p.P0[3, :, 1] = 0.0
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+    ff.fca_set_option(ctx, "check_finite", 1)
+    with pytest.raises(ff.FcaError) as e:
+        ff.fastfca_as_iterate(ctx, 1)
+    assert e.value.status == (ff.FCA_ERR_SINGULAR if case == "P_zero_column" else ff.FCA_ERR_ARG), case
+    ff.fca_set_params(ctx, good["v0"], good["lam0"], good["P0"])
+    ff.fastfca_as_iterate(ctx, 1)
+
+
+@pytest.mark.parametrize("path", [1, 2], ids=["resident", "streaming"])
+def test_zero_bin_reports_a_singular_solve(ff, path):
+    """A bin whose mixture is zero at every frame makes the weighted
+    covariances of eq. 23 zero: with "check_finite" the iterate call reports
+    FCA_ERR_SINGULAR (the kernels still complete; that bin's P is not
+    finite), without it the call succeeds and the other bins are updated
+    as usual."""
+    p = problem(3, 3, 5, 90, seed=4)
+    p.x[2] = 0.0
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+    ff.fca_set_option(ctx, "path", path)
+    ff.fca_set_option(ctx, "check_finite", 1)
+    with pytest.raises(ff.FcaError) as e:
+        ff.fastfca_as_iterate(ctx, 1)
+    assert e.value.status == ff.FCA_ERR_SINGULAR
+    other = np.array([0, 1, 3, 4])
+    ref = oracle_as_bounded(synth_sub(p, other), 1)
+    v, lam, P = params(ff, ctx)
+    check_as_params((v[other], lam[other], P[other]), ref, tag=f" zero bin path {path}")
+
+
+def synth_sub(p, bins):
+    from tests.gpu_common import sub_problem
+    return sub_problem(p, bins)
+
+
+@pytest.mark.parametrize("case", ["S_negative", "S_zero", "v_zero"])
+def test_em_parameter_check_on_the_device(ff, case):
+    """FCA EM contexts: v > 0 and every S_j(f) positive definite, checked on
+    the device by the first iterate call with "check_finite"."""
+    p = problem(3, 2, 4, 60, seed=5)
+    S0 = oracle.as_spatial_cov(p.P0, p.lam0)
+    if case == "S_negative":
+        S0[2, 1] = -np.eye(3)
+    elif case == "S_zero":
+        S0[0, 0] = 0.0
+    else:
+        p.v0[3, 10, 1] = 0.0
+    t = to_dev(p, S0)
+    ctx = ff.fca_init(ff.FCA_METHOD_EM, t["x"], t["v0"], t["lam0"], t["P0"], t["R0"])
+    ff.fca_set_option(ctx, "check_finite", 1)
+    with pytest.raises(ff.FcaError) as e:
+        ff.fca_em_iterate(ctx, 1)
+    assert e.value.status == (ff.FCA_ERR_ARG if case == "v_zero" else ff.FCA_ERR_SINGULAR), case

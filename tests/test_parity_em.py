@@ -11,8 +11,8 @@ import pytest
 import oracle
 from paper_1805_09498_amd import synth
 from tests import error_bounds as EB
-from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, check, check_loglik_bins, oracle_em, params, problem, rel,
-                              sub_problem, to_dev)
+from tests.gpu_common import (TOL_LOGLIK, TOL_PARAM, check, check_loglik_bins, oracle_em, oracle_em_bounded, params,
+                              problem, rel, sub_problem, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -93,12 +93,17 @@ def test_ten_iterations_loglik(ff, cfg, path):
     ctx = run_em(ff, p, 10, path=path)
     L = ff.fca_loglik(ctx)
     Lb = ff.fca_loglik_bins(ctx).cpu().numpy()
-    v_ref, R_ref = oracle_em(p, oracle.as_spatial_cov(p.P0, p.lam0), 10)
+    v_ref, R_ref, _, rho = oracle_em_bounded(p, oracle.as_spatial_cov(p.P0, p.lam0), 10)
     Lb_ref = oracle.loglik_fca(p.x, v_ref, R_ref, per_bin=True)
     L_ref = float(Lb_ref.sum())
     print(L, L_ref, abs(L - L_ref) / abs(L_ref))
     assert abs(L - L_ref) <= TOL_LOGLIK * abs(L_ref)
-    check_loglik_bins(Lb, Lb_ref, tag=f" em {cfg['F']}x{cfg['N']} path {path}")
+    # the accumulated relative state bound times the sensitivity of L1, plus
+    # an FP32 evaluation of its terms (I + 2 logarithms and a quadratic form
+    # per point, relative to the same sensitivity)
+    sens = EB.em_loglik_bin_sensitivity(p.x, v_ref, R_ref)
+    check_loglik_bins(Lb, Lb_ref, (rho + EB.gamma(8 * p.x.shape[2] + 8)) * sens,
+                      tag=f" em {cfg['F']}x{cfg['N']} path {path}")
 
 
 def test_same_start_as_fastfca(ff):
