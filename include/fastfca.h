@@ -319,6 +319,33 @@ fca_status fca_stft(const float *wav, int C, int L, int frame, int hop, fca_c64 
 fca_status fca_istft(const fca_c64 *S, int J, int C, int N, int frame, int hop, int L, float *wav,
                      void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free run, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It allocates nothing: the working storage (the repacked
+ * mixture and v, the per-tile partial sums, the log-likelihood partials)
+ * lives in a library array of FCA_NOALLOC_SCRATCH_BYTES per device, held
+ * from the first call on a device until the process ends.
+ * ------------------------------------------------------------------------ */
+#define FCA_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* n_iter FastFCA-AS hybrid iterations (K = 1, the fixed-point P update),
+ * as fca_init + fastfca_as_iterate + fca_get_params would run them, on the
+ * caller's parameters in place: x [F][N][I] (device, read), v [F][N][J],
+ * lam [F][J][I], P [F][I][I] (device, read and overwritten with the state
+ * after the iterations).  loglik: NULL, or a device double that receives L2
+ * (eq. 14) of the final state.  The launch shape is fixed (the first
+ * frequency-resident shape of (4 waves, 2 bins), (4, 1), (2, 1), (1, 1) that
+ * holds N frames, else the streaming kernels on hip_stream alone), so the
+ * results equal those of a context forced to the same shape.  Checks as
+ * fca_init, and FCA_ERR_ARG when the working storage,
+ * 4 (2I + J) F ceil64(N) bytes plus the partial sums, exceeds
+ * FCA_NOALLOC_SCRATCH_BYTES; messages in fca_last_error(NULL).  Calls
+ * overlapping on one device share the array and race: serialise them (one
+ * stream, or events).  Asynchronous; calls no allocating routine. */
+fca_status fastfca_as_run_noalloc(int F, int N, int I, int J, const fca_c64 *x, float *v, float *lam,
+                                  fca_c64 *P, int n_iter, double *loglik, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

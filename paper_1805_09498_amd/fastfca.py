@@ -9,7 +9,8 @@ The functions carry the names of the C ABI (include/fastfca.h):
 ``fca_destroy``, the batch calls ``fca_batch_*`` and the derivative calls
 ``fastfca_as_forward`` / ``fastfca_as_backward`` (``autograd.py`` wraps them
 in a ``torch.autograd.Function``) and the STFT calls ``fca_stft_shape``,
-``fca_stft``, ``fca_istft``.
+``fca_stft``, ``fca_istft``, and ``fastfca_as_run_noalloc`` (no context, no
+device allocation).
 Arrays are torch tensors on the GPU in the ABI layouts (complex64 /
 float32, C-contiguous); PyTorch provides the device memory and the stream.
 
@@ -41,7 +42,8 @@ EXPORTED = ("fca_init", "fastfca_as_iterate", "fca_em_iterate", "fca_wiener_sepa
             "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
             "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
             "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
-            "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft")
+            "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft",
+            "fastfca_as_run_noalloc")
 
 
 def _load():
@@ -105,6 +107,8 @@ def _load():
     lib.fca_stft.restype = i
     lib.fca_istft.argtypes = [vp, i, i, i, i, i, i, vp, vp]
     lib.fca_istft.restype = i
+    lib.fastfca_as_run_noalloc.argtypes = [i, i, i, i, vp, vp, vp, vp, i, vp, vp]
+    lib.fastfca_as_run_noalloc.restype = i
     return lib
 
 
@@ -418,3 +422,18 @@ def fca_istft(S, L, frame=1024, hop=512, stream=None):
                          ctypes.c_void_p(wav.data_ptr()), sh))
     return wav
 
+
+def fastfca_as_run_noalloc(x, v, lam, P, n_iter, loglik=None, stream=None):
+    """n_iter iterations on the caller's (v, lam, P) in place, no context and
+    no device allocation by the library: x [F][N][I] complex64, v [F][N][J]
+    float32, lam [F][J][I] float32, P [F][I][I] complex64; loglik None or a
+    one-element float64 tensor that receives L2 of the final state."""
+    if x.dim() != 3 or v.dim() != 3:
+        raise ValueError("x must be [F][N][I] and v [F][N][J]")
+    F, N, I = x.shape
+    J = v.shape[2]
+    sh, _ = _stream_handle(stream)
+    _check(lib.fastfca_as_run_noalloc(
+        F, N, I, J, _ptr(x, torch.complex64, (F, N, I), "x"), _ptr(v, torch.float32, (F, N, J), "v"),
+        _ptr(lam, torch.float32, (F, J, I), "lam"), _ptr(P, torch.complex64, (F, I, I), "P"), int(n_iter),
+        _ptr(loglik, torch.float64, (1,), "loglik"), sh))

@@ -48,7 +48,8 @@ def test_header_declares_the_expected_calls():
         "fca_get_option", "fca_set_option_f64", "fca_get_option_f64", "fca_last_error", "fca_destroy",
         "fca_batch_init", "fca_batch_iterate", "fca_batch_context", "fca_batch_set_option",
         "fca_batch_get_option", "fca_batch_last_error", "fca_batch_destroy",
-        "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft"])
+        "fastfca_as_forward", "fastfca_as_backward", "fca_stft_shape", "fca_stft", "fca_istft",
+        "fastfca_as_run_noalloc"])
 
 
 def test_every_declared_function_is_exported(lib):
@@ -154,6 +155,26 @@ def test_stft_rejects_bad_frames_on_the_host(lib, W, H):
     assert lib.fca_stft(FAKE, 2, 1000, W, H, FAKE, None) == -1
     lib.fca_istft.argtypes = [vp, i, i, i, i, i, i, vp, vp]
     assert lib.fca_istft(FAKE, 2, 2, 3, W, H, 1000, FAKE, None) == -1
+
+
+def test_noalloc_run_rejects_on_the_host(lib):
+    """The allocation-free run checks its arguments and the size of its
+    working storage before any device call (fake, never dereferenced
+    pointers)."""
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    lib.fastfca_as_run_noalloc.argtypes = [i, i, i, i, vp, vp, vp, vp, i, vp, vp]
+    lib.fastfca_as_run_noalloc.restype = i
+    fake = vp(1 << 20)
+    run = lambda F, N, I, J, n_iter=1, ll=None: lib.fastfca_as_run_noalloc(F, N, I, J, fake, fake, fake, fake,
+                                                                          n_iter, ll, None)
+    assert run(1500, 4000, 8, 6) == -1                     # needs more than FCA_NOALLOC_SCRATCH_BYTES
+    assert b"working storage" in lib.fca_last_error(None)
+    assert run(4, 10, 3, 3, n_iter=-1) == -1
+    assert run(4, 2, 3, 3) == -1                           # N < I
+    assert run(4, 10, 9, 3) == -2                          # I outside the instantiated range
+    assert run(4, 10, 3, 3, ll=vp((1 << 20) + 4)) == -1    # misaligned log-likelihood pointer
+    lib.fastfca_as_run_noalloc.argtypes = [i, i, i, i, vp, vp, vp, vp, i, vp, vp]
+    assert lib.fastfca_as_run_noalloc(4, 10, 3, 3, None, fake, fake, fake, 1, None, None) == -1
 
 
 def test_status_codes_of_header_and_binding_agree():
