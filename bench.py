@@ -534,6 +534,10 @@ def main():
             "source": "Section 5 (Figure of the real-time factor) and the abstract"}
     if not args.no_fwd_bwd:
         res["fwd_bwd"] = fwd_bwd_leg(ff, *tens, args.fwd_bwd_iters, args.ckpt_every, max(3, args.steps // 4), 2)
+        # the same with one segment: the forward run records every state
+        # (a tape of about 0.1 GB at this shape), so the reverse pass recomputes none
+        res["fwd_bwd"]["full_tape"] = fwd_bwd_leg(ff, *tens, args.fwd_bwd_iters, args.fwd_bwd_iters,
+                                                  max(3, args.steps // 4), 2)
     if not args.no_extra:
         res["paper_shape"] = workload_leg(ff, "paper", max(3, args.steps // 2), 2, 2 if not args.no_em else 0)
         for name in ("long6x4", "long8x6"):

@@ -50,6 +50,27 @@ __device__ __forceinline__ void as_transform(const float (&Pr)[I][I], const floa
   }
 }
 
+// The part of as_point_em after e_i: W_j, the v update and the eq. 20 sums.
+template <int I, int J>
+__device__ __forceinline__ void as_point_em_e(const float (&e)[I], const float (&lamI)[J][I], float (&v)[J],
+                                              float (&S0)[J], float (&S1)[J][I], bool take) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    float u = lamI[j][0] * e[0];
+#pragma unroll
+    for (int i = 1; i < I; ++i) u = fmaf(lamI[j][i], e[i], u);
+    const float W = fmaf(v[j], u, 1.0f);
+    // A lane that does not own a frame (take = false) keeps its v, so that
+    // padded lanes stay finite over any number of iterations.
+    const float rW = take ? rcp(W) : 0.f;
+    const float m = v[j] * rW;
+    S0[j] += rW;
+#pragma unroll
+    for (int i = 0; i < I; ++i) S1[j][i] = fmaf(m, e[i], S1[j][i]);
+    v[j] = take ? v[j] * W : v[j];
+  }
+}
+
 // E-step statistics and v update of one point, in a form with fewer
 // operations that is algebraically identical to eq. 16-17, 19 and 20:
 //   d_i = sum_j v_j lambda_ji,   g_ji = v_j lambda_ji / d_i  (diagonal Wiener gain),
@@ -75,21 +96,20 @@ __device__ __forceinline__ void as_point_em(const float (&y2)[I], const float (&
     const float t = rcp(d);
     e[i] = fmaf(y2[i], t, -1.0f) * t;
   }
+  as_point_em_e<I, J>(e, lamI, v, S0, S1, take);
+}
+
+// The same with the reciprocals rd_i = 1 / d_i given (phase B of the
+// previous iteration forms them as its eq. 23 weights, from the same v and
+// lambda with the same operations, so the result is bitwise that of
+// as_point_em).
+template <int I, int J>
+__device__ __forceinline__ void as_point_em_rd(const float (&y2)[I], const float (&rd)[I], const float (&lamI)[J][I],
+                                               float (&v)[J], float (&S0)[J], float (&S1)[J][I], bool take) {
+  float e[I];
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    float u = lamI[j][0] * e[0];
-#pragma unroll
-    for (int i = 1; i < I; ++i) u = fmaf(lamI[j][i], e[i], u);
-    const float W = fmaf(v[j], u, 1.0f);
-    // A lane that does not own a frame (take = false) keeps its v, so that
-    // padded lanes stay finite over any number of iterations.
-    const float rW = take ? rcp(W) : 0.f;
-    const float m = v[j] * rW;
-    S0[j] += rW;
-#pragma unroll
-    for (int i = 0; i < I; ++i) S1[j][i] = fmaf(m, e[i], S1[j][i]);
-    v[j] = take ? v[j] * W : v[j];
-  }
+  for (int i = 0; i < I; ++i) e[i] = fmaf(y2[i], rd[i], -1.0f) * rd[i];
+  as_point_em_e<I, J>(e, lamI, v, S0, S1, take);
 }
 
 // Number of eq. 20 partial sums per bin or tile: S0 (J), then S1 (J x I).

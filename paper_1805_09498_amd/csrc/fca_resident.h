@@ -88,7 +88,8 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
   const int f = f0 + bin;
   const int T = nw * kWave;                                // lanes per bin
   const int tb = wl * kWave + (int)(threadIdx.x & (kWave - 1));  // lane index within the bin
-  const int c = tb % I;                                    // the column of eq. 23 this lane solves
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int c = lane % I;                                  // the column of eq. 23 this lane solves
   // first frame of this wave's slot 0; a slot k is skipped by the whole wave
   // when wbase + k T >= N (a scalar branch)
   const int wbase = wl * kWave;
@@ -109,9 +110,13 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
   float* vf = s.vs + (size_t)f * J * s.Npad;
   float xr[kXReg ? NPT : 1][I], xi[kXReg ? NPT : 1][I], v[NPT][J];
   float yr[NPT][I], yi[NPT][I];  // y = P^H x of the current iteration (phase A -> B)
-  // |y_i|^2 is kept for phase B as well where the registers allow
-  constexpr bool kKeepY2 = kOnePass && NPT <= 8 && !kGen;
-  float y2k[kKeepY2 ? NPT : 1][I];
+  // Where the registers allow, phase B keeps its eq. 23 weights 1 / d_i
+  // (from the updated v and lambda) for the next iteration's phase A, whose
+  // d_i are the same sums: the E-step then forms no d_i and no reciprocal.
+  // (not in the recording variant, whose trace addresses take those
+  // registers: there it would cost the second workgroup per CU).
+  constexpr bool kKeepRd = kOnePass && NPT <= 8 && !kGen && !kTrace;
+  float rdk[kKeepRd ? NPT : 1][I];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tb + k * T;
@@ -128,6 +133,16 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
   }
   __syncthreads();
   const float invN = 1.0f / float(s.N);
+  if constexpr (kKeepRd) {
+    float lam0[J][I];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int i = 0; i < I; ++i) lam0[j][i] = sLam[bin][j * I + i];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      if (wbase + k * T < s.N) as_point_weights<I, J>(lam0, v[k], rdk[k]);
+  }
 
 #pragma unroll 1
   for (int it = 0; it < n_iter; ++it) {
@@ -176,15 +191,18 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           float y2[I];
 #pragma unroll
           for (int i = 0; i < I; ++i) y2[i] = fmaf(yr[k][i], yr[k][i], yi[k][i] * yi[k][i]);
-          if constexpr (kKeepY2) {
-#pragma unroll
-            for (int i = 0; i < I; ++i) y2k[k][i] = y2[i];
-          }
           // a slot every lane of the wave owns skips the per-lane selects
-          if (wbase + k * T + kWave <= s.N)
-            as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, true);
-          else
-            as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, ok);
+          if constexpr (kKeepRd) {
+            if (wbase + k * T + kWave <= s.N)
+              as_point_em_rd<I, J>(y2, rdk[k], lamI, v[k], S0, S1, true);
+            else
+              as_point_em_rd<I, J>(y2, rdk[k], lamI, v[k], S0, S1, ok);
+          } else {
+            if (wbase + k * T + kWave <= s.N)
+              as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, true);
+            else
+              as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, ok);
+          }
         }
       }
       float flat[kEq20Sums<I, J>];
@@ -224,9 +242,9 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           float w[I], z[I * I];
           as_point_weights<I, J>(lam, v[k], w);
           herm_outer<I>(z, yr[k], yi[k]);
-          if constexpr (kKeepY2) {
+          if constexpr (kKeepRd) {
 #pragma unroll
-            for (int a = 0; a < I; ++a) z[a * I + a] = y2k[k][a];
+            for (int a = 0; a < I; ++a) rdk[k][a] = w[a];
           }
 #pragma unroll
           for (int i = 0; i < I; ++i)
@@ -299,9 +317,11 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 #pragma unroll
       for (int q = 0; q < J * I; ++q) sLam[bin][q] = lam[q / I][q % I];
     }
-    // The bin's first wave solves (lane c: column c); the other waves go
-    // straight to the barrier that publishes the new P.
-    if (wl == 0) {
+    // One wave of the bin solves (lane c: column c); the other waves go
+    // straight to the barrier that publishes the new P.  The solving wave
+    // rotates with the iteration, so that on a CU whose SIMDs host waves of
+    // two workgroups the serial solves land on every SIMD in turn.
+    if (wl == it % nw) {
       // S_c = N G_c (upper triangle); column c of A solves S_c a = N e_c.
       // packed: real parts on and above, imaginary parts below the diagonal
       float Sr[I][I], Si[I][I];
@@ -312,7 +332,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 #pragma unroll
       for (int a = 0; a < I; ++a) Si[a][a] = 0.f;
       if constexpr (kTrace) {
-        if (tb < I) {  // S_c packed: real parts on and above, imaginary parts below the diagonal
+        if (lane < I) {  // S_c packed: real parts on and above, imaginary parts below the diagonal
           float* dst = tr.S + (size_t)it * tr.sstride + ((size_t)f * I + c) * I * I;
 #pragma unroll
           for (int a = 0; a < I; ++a)
@@ -346,7 +366,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       } else {
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] = (a == c) ? fN : 0.f; ai[a] = 0.f; }
-        if (!herm_solve<I>(Sr, Si, ar, ai) && tb < I) atomicOr(s.flag, kFlagSingular);
+        if (!herm_solve<I>(Sr, Si, ar, ai) && lane < I) atomicOr(s.flag, kFlagSingular);
       }
       // K > 1: further fixed-point steps a_c = G_c^-1 [A^-H]_c; lane b holds
       // column b of the current A, gathered with readlane (no LDS, no
@@ -367,7 +387,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
         pinvh_col<I, float>(A2r, A2i, c, ar, ai);
 #pragma unroll
         for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
-        if (!herm_solve<I>(Sr, Si, ar, ai) && tb < I) atomicOr(s.flag, kFlagSingular);
+        if (!herm_solve<I>(Sr, Si, ar, ai) && lane < I) atomicOr(s.flag, kFlagSingular);
       }
       // p_c = P_old a_c; P_old is read from LDS again (the copy in registers
       // from phase A is not kept alive through phase B).  Lane c < I writes
@@ -411,7 +431,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           }
         }
       }
-      if (tb < I) {
+      if (lane < I) {
 #pragma unroll
         for (int a = 0; a < I; ++a) { sPr[bin][a][c] = pnr[a]; sPi[bin][a][c] = pni[a]; }
       }
