@@ -38,6 +38,15 @@ constexpr int kAdjBlock = (I <= 3) ? 256 : 128;
 template <int I>
 constexpr bool kAdjPrefetch = (I <= 5);
 
+// Pass 1 of the iteration adjoint forms alpha_i, beta_i, w_i and d'bar_i of
+// every frame; where a bin's frames fit, it keeps them in LDS (6I floats per
+// frame in float4 planes, plane-major so that lanes store consecutively) for
+// pass 2, which would otherwise form them again.  The share of LDS is what
+// three workgroups per CU leave each (their registers allow three).
+template <int I>
+constexpr int kAdjStashPlanes = (6 * I + 3) / 4;
+constexpr int kAdjStashBytes = 52 * 1024;
+
 template <int I, int J>
 constexpr int adj_red_size() {
   constexpr int a = pad4((I * I * I <= 64) ? I * I * I : I * I);
@@ -84,9 +93,11 @@ __device__ __forceinline__ void adj_load_x_at(const float* xf, int Npad, unsigne
 // ----------------------------------------------------------------------------
 // Adjoint of one hybrid iteration (K = 1).
 // ----------------------------------------------------------------------------
-template <int I, int J>
+template <int I, int J, bool kStash>
 __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a) {
   constexpr bool kOne = I * I * I <= 64;
+  constexpr int SP = kAdjStashPlanes<I>;
+  extern __shared__ float4 sStash[];  // [SP][N] when kStash
   constexpr int kB = kAdjBlock<I>, PH = kPH<I>;
   const int f = blockIdx.x, tid = threadIdx.x;
   const int N = s.N, Np = s.Npad;
@@ -333,6 +344,19 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
       for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int i = 0; i < I; ++i) acc[j * I + i] = fmaf(dpb[i], vN[j], acc[j * I + i]);
+      if constexpr (kStash) {
+        float st[4 * SP];
+#pragma unroll
+        for (int i = 0; i < I; ++i) {
+          st[i] = alr[i]; st[I + i] = ali[i]; st[2 * I + i] = ber[i];
+          st[3 * I + i] = bei[i]; st[4 * I + i] = w[i]; st[5 * I + i] = dpb[i];
+        }
+#pragma unroll
+        for (int k = 6 * I; k < 4 * SP; ++k) st[k] = 0.f;
+#pragma unroll
+        for (int q = 0; q < SP; ++q)
+          sStash[q * N + n] = make_float4(st[4 * q], st[4 * q + 1], st[4 * q + 2], st[4 * q + 3]);
+      }
     }
     if (kAdjPrefetch<I> && tid < N) load2(tid, qxr, qxi, qvN, qv, qvb, qxbr, qxbi);  // first frame of pass 2
     block_sum_t<J * I>(acc, sLb, red);
@@ -365,8 +389,22 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
     unsigned u = 4u * n;
     asm volatile("" : "+s"(zo), "+v"(u));
     as_transform_lds<I>(sPc + zo, xr, xi, yr, yi);
-    weights(sLm + zo, vN, w);
-    dprime_bar(sAB + zo, yr, yi, w, alr, ali, ber, bei, dpb);
+    if constexpr (kStash) {  // pass 1's values of this frame (same lane, written before the barrier)
+      float st[4 * SP];
+#pragma unroll
+      for (int q = 0; q < SP; ++q) {
+        const float4 t = sStash[q * N + n];
+        st[4 * q] = t.x; st[4 * q + 1] = t.y; st[4 * q + 2] = t.z; st[4 * q + 3] = t.w;
+      }
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        alr[i] = st[i]; ali[i] = st[I + i]; ber[i] = st[2 * I + i];
+        bei[i] = st[3 * I + i]; w[i] = st[4 * I + i]; dpb[i] = st[5 * I + i];
+      }
+    } else {
+      weights(sLm + zo, vN, w);
+      dprime_bar(sAB + zo, yr, yi, w, alr, ali, ber, bei, dpb);
+    }
     // with h_i = |y_i|^2 / d_i - 1 and q = v lambda, g = q / d:
     //   r = q (1 + g h),  dr/dq = 1 + 2 g h,  dr/dd = -g^2 (1 + 2 h),  dr/d|y|^2 = g^2
     float id[I], h[I], m2[I];  // 1 / d_i, h_i, -(1 + 2 h_i)
@@ -679,7 +717,11 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_wiener(DevState s, const f
 
 template <int I, int J>
 hipError_t launch_adj_iter(const DevState& s, const AdjIter& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_adj_iter<I, J>), dim3(s.F), dim3(kAdjBlock<I>), 0, st, s, a);
+  const size_t stash = sizeof(float4) * kAdjStashPlanes<I> * (size_t)s.N;
+  if (stash <= (size_t)kAdjStashBytes)
+    hipLaunchKernelGGL((k_adj_iter<I, J, true>), dim3(s.F), dim3(kAdjBlock<I>), stash, st, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_iter<I, J, false>), dim3(s.F), dim3(kAdjBlock<I>), 0, st, s, a);
   return hipGetLastError();
 }
 

@@ -168,7 +168,8 @@ template <int I, int J>
 __device__ __forceinline__ float eq20_from_tiles(const DevState& s, int f, int t, float lam, float invN) {
   constexpr int V = kEq20Sums<I, J>;
   float s0 = 0.f, s1 = 0.f;
-  for (int c = 0; c < s.nchunk; ++c) {
+#pragma unroll 4
+  for (int c = 0; c < s.nchunk; ++c) {  // unrolled: the tiles' loads in flight together
     const float* src = s.partA + ((size_t)f * s.nchunk + c) * V;
     s0 += src[t / I];
     s1 += src[J + t];
@@ -630,6 +631,8 @@ hipError_t launch_as_loglik(const DevState& s, hipStream_t st) {
 // at each use (their 2 x 128 values in registers left one wave per SIMD).
 template <int I>
 constexpr bool kWienerPinLds = (I >= 7);
+using v4f = float __attribute__((ext_vector_type(4)));
+using v2f = float __attribute__((ext_vector_type(2)));
 
 template <int I, int J, bool kVec4>
 __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __restrict__ out) {
@@ -733,13 +736,26 @@ __global__ __launch_bounds__(kBlock) void k_as_wiener(DevState s, float2* __rest
 #pragma unroll
         for (int r = 0; r < I / 2; ++r) {
           const int q = lane + r * kWave;
-          if (2 * q < rows) o4[q] = t4[q];
+          if (2 * q < rows) {
+            // streamed out, never re-read: non-temporal stores where they
+            // measured faster (I = 6: 187 -> 168 us at the 60 s shape; at I = 8
+            // they took 374 -> 394 us, so there the stores stay ordinary)
+            if constexpr (!kLds)
+              __builtin_nontemporal_store(reinterpret_cast<const v4f*>(t4)[q], reinterpret_cast<v4f*>(o4) + q);
+            else
+              o4[q] = t4[q];
+          }
         }
       } else {
 #pragma unroll
         for (int r = 0; r < I; ++r) {
           const int q = lane + r * kWave;
-          if (q < rows) o[q] = tile[q];
+          if (q < rows) {
+            if constexpr (!kLds)
+              __builtin_nontemporal_store(reinterpret_cast<const v2f*>(tile)[q], reinterpret_cast<v2f*>(o) + q);
+            else
+              o[q] = tile[q];
+          }
         }
       }
       __builtin_amdgcn_wave_barrier();

@@ -321,7 +321,13 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
     // straight to the barrier that publishes the new P.  The solving wave
     // rotates with the iteration, so that on a CU whose SIMDs host waves of
     // two workgroups the serial solves land on every SIMD in turn.
-    if (wl == it % nw) {
+    if (wl == (it & (nw - 1))) {  // nw is 1, 2 or 4
+      // P_old for p_c = P_old a_c, requested before the solve's chain
+      float Por[I][I], Poi[I][I];
+#pragma unroll
+      for (int a = 0; a < I; ++a)
+#pragma unroll
+        for (int b = 0; b < I; ++b) { Por[a][b] = sPr[bin][a][b]; Poi[a][b] = sPi[bin][a][b]; }
       // S_c = N G_c (upper triangle); column c of A solves S_c a = N e_c.
       // packed: real parts on and above, imaginary parts below the diagonal
       float Sr[I][I], Si[I][I];
@@ -389,15 +395,15 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
         for (int a = 0; a < I; ++a) { ar[a] *= fN; ai[a] *= fN; }
         if (!herm_solve<I>(Sr, Si, ar, ai) && lane < I) atomicOr(s.flag, kFlagSingular);
       }
-      // p_c = P_old a_c; P_old is read from LDS again (the copy in registers
+      // p_c = P_old a_c (P_old read from LDS above: the copy in registers
       // from phase A is not kept alive through phase B).  Lane c < I writes
-      // column c only after every lane of the wave has read row a.
+      // column c of the LDS copy below, after every lane has read it.
 #pragma unroll
       for (int a = 0; a < I; ++a) {
         float pr = 0.f, pi = 0.f;
 #pragma unroll
         for (int b = 0; b < I; ++b) {
-          const float qr = sPr[bin][a][b], qi = sPi[bin][a][b];
+          const float qr = Por[a][b], qi = Poi[a][b];
           pr = fmaf(qr, ar[b], pr);
           pr = fmaf(-qi, ai[b], pr);
           pi = fmaf(qr, ai[b], pi);
