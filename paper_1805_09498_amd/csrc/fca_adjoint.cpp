@@ -5,7 +5,8 @@
 // The backward pass walks the checkpoint segments from the last to the
 // first: it rebuilds the states of a segment from its checkpoint with the
 // same workgroup body and launch shape as the recorded run, then runs the
-// adjoint of each iteration in reverse order.  With the frequency-resident
+// adjoints of its iterations in reverse order in one launch (a workgroup
+// carries its bin through the segment).  With the frequency-resident
 // kernel one launch of its recording variant rebuilds a whole segment and
 // also keeps the eq. 23 sums of every iteration for the adjoint; with the
 // streaming kernels the segment is rebuilt one iteration at a time and the
@@ -213,19 +214,19 @@ fca_status fastfca_as_backward(fca_ctx* c, const fca_c64* grad_out, fca_c64* gra
           return fca::ctx_hip_fail(c, e, "segment recompute");
       }
     }
-    for (int j = len - 1; j >= 0; --j) {
-      const StateView st = state_at(c, t, slot_at(j));
-      const StateView sn = state_at(c, t, slot_at(j + 1));
-      AdjIter a{};
-      a.S_t = recorded ? tape + t.S_off + (size_t)j * t.S_floats : nullptr;
-      a.v_t = st.v; a.lam_t = st.lam; a.P_t = st.P;
-      a.v_n = sn.v; a.lam_n = sn.lam;
-      a.vb_in = vb[cur]; a.lb_in = lb[cur]; a.Pb_in = Pb[cur];
-      a.vb_out = vb[1 - cur]; a.lb_out = lb[1 - cur]; a.Pb_out = Pb[1 - cur];
-      a.xb = xb;
-      if ((e = c->ks->adj_iter(c->s, a, c->stream)) != hipSuccess) return fca::ctx_hip_fail(c, e, "iteration adjoint");
-      cur = 1 - cur;
-    }
+    // the segment's iteration adjoints, last first, in one launch
+    fca::AdjSeg g{};
+    g.tape = tape;
+    g.ck = (long long)ck_at; g.slot0 = (long long)t.slot_off; g.stride = (long long)t.state_floats;
+    g.v_off = (long long)t.v_off; g.lam_off = (long long)t.lam_off; g.P_off = (long long)t.P_off;
+    g.S = recorded ? tape + t.S_off : nullptr;
+    g.S_floats = (long long)t.S_floats;
+    for (int k = 0; k < 2; ++k) { g.vb[k] = vb[k]; g.lb[k] = lb[k]; g.Pb[k] = Pb[k]; }
+    g.xb = xb;
+    g.len = len; g.cur = cur;
+    if (len > 0 && (e = c->ks->adj_seg(c->s, g, c->stream)) != hipSuccess)
+      return fca::ctx_hip_fail(c, e, "iteration adjoints");
+    if (len & 1) cur = 1 - cur;
   }
   e = hipSuccess;
   if (grad_x) e = fca::launch_unpack_x(xb, reinterpret_cast<float2*>(grad_x), c->F, c->N, c->I, c->s.Npad, c->stream);

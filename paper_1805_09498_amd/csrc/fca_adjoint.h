@@ -94,7 +94,7 @@ __device__ __forceinline__ void adj_load_x_at(const float* xf, int Npad, unsigne
 // Adjoint of one hybrid iteration (K = 1).
 // ----------------------------------------------------------------------------
 template <int I, int J, bool kStash>
-__global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a) {
+__device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& a) {
   constexpr bool kOne = I * I * I <= 64;
   constexpr int SP = kAdjStashPlanes<I>;
   extern __shared__ float4 sStash[];  // [SP][N] when kStash
@@ -532,6 +532,45 @@ __global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a
   }
 }
 
+template <int I, int J, bool kStash>
+__global__ __launch_bounds__(kAdjBlock<I>) void k_adj_iter(DevState s, AdjIter a) {
+  adj_iter_body<I, J, kStash>(s, a);
+}
+
+// The inputs and outputs of the adjoint of iteration j of a segment whose
+// adjoints alternate between the two buffers, `cur` being read at j.
+__host__ __device__ inline AdjIter adj_seg_iter(const AdjSeg& g, int j, int cur) {
+  const long long st = j == 0 ? g.ck : g.slot0 + j * g.stride;
+  const long long sn = g.slot0 + (j + 1) * g.stride;
+  AdjIter a;
+  a.S_t = g.S ? g.S + j * g.S_floats : nullptr;
+  a.v_t = g.tape + st + g.v_off;
+  a.lam_t = g.tape + st + g.lam_off;
+  a.P_t = reinterpret_cast<const float2*>(g.tape + st + g.P_off);
+  a.v_n = g.tape + sn + g.v_off;
+  a.lam_n = g.tape + sn + g.lam_off;
+  a.vb_in = g.vb[cur]; a.lb_in = g.lb[cur]; a.Pb_in = g.Pb[cur];
+  a.vb_out = g.vb[1 - cur]; a.lb_out = g.lb[1 - cur]; a.Pb_out = g.Pb[1 - cur];
+  a.xb = g.xb;
+  return a;
+}
+
+// The adjoints of iterations len-1 .. 0 of one checkpoint segment in one
+// launch.  Bins never interact, so a workgroup takes its bin through the
+// whole segment: what one iteration's adjoint hands the next (v'bar,
+// lambda'bar, P'bar, xbar of this bin) goes through global memory, written
+// and read by this workgroup only, ordered by the barrier between them.
+template <int I, int J, bool kStash>
+__global__ __launch_bounds__(kAdjBlock<I>) void k_adj_seg(DevState s, AdjSeg g) {
+  int cur = g.cur;
+#pragma unroll 1
+  for (int j = g.len - 1; j >= 0; --j) {
+    adj_iter_body<I, J, kStash>(s, adj_seg_iter(g, j, cur));
+    cur = 1 - cur;
+    __syncthreads();  // this bin's outputs before the next iteration reads them
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Adjoint of the Wiener filter s_j = P^-H (g_j o y), g_ji = v_j lambda_ji / d_i
 // (B = P^-H is formed in the workgroup).  gout [J][F][N][I]; writes vb_out, lb_out, Pb_out
@@ -723,6 +762,35 @@ hipError_t launch_adj_iter(const DevState& s, const AdjIter& a, hipStream_t st) 
   else
     hipLaunchKernelGGL((k_adj_iter<I, J, false>), dim3(s.F), dim3(kAdjBlock<I>), 0, st, s, a);
   return hipGetLastError();
+}
+
+// One launch for the segment when every bin's workgroup is resident at once
+// (a workgroup that had to wait for another to finish its whole segment
+// would double the time); otherwise one launch per iteration.
+template <int I, int J, bool kStash>
+hipError_t launch_adj_seg_k(const DevState& s, const AdjSeg& g, hipStream_t st, size_t shm) {
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_seg<I, J, kStash>, kAdjBlock<I>, shm);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if ((long long)per_cu * cus >= s.F) {
+    hipLaunchKernelGGL((k_adj_seg<I, J, kStash>), dim3(s.F), dim3(kAdjBlock<I>), shm, st, s, g);
+    return hipGetLastError();
+  }
+  int cur = g.cur;
+  for (int j = g.len - 1; j >= 0; --j) {
+    if ((e = launch_adj_iter<I, J>(s, adj_seg_iter(g, j, cur), st)) != hipSuccess) return e;
+    cur = 1 - cur;
+  }
+  return hipSuccess;
+}
+
+template <int I, int J>
+hipError_t launch_adj_seg(const DevState& s, const AdjSeg& g, hipStream_t st) {
+  const size_t stash = sizeof(float4) * kAdjStashPlanes<I> * (size_t)s.N;
+  return stash <= (size_t)kAdjStashBytes ? launch_adj_seg_k<I, J, true>(s, g, st, stash)
+                                         : launch_adj_seg_k<I, J, false>(s, g, st, 0);
 }
 
 template <int I, int J>

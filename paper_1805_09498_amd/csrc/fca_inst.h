@@ -18,7 +18,8 @@ const KernelSet* FCA_CAT4(kernel_set_I, FCA_I, _J, FCA_J)() {
       &launch_as_wiener<FCA_I, FCA_J>,      &launch_em_wiener<FCA_I, FCA_J>,
       &launch_em_from_as<FCA_I, FCA_J>,     &launch_em_rinv<FCA_I, FCA_J>,
       &launch_as_iter_resident_trace<FCA_I, FCA_J>,
-      &launch_adj_iter<FCA_I, FCA_J>,       &launch_adj_wiener<FCA_I, FCA_J>,
+      &launch_adj_iter<FCA_I, FCA_J>,       &launch_adj_seg<FCA_I, FCA_J>,
+      &launch_adj_wiener<FCA_I, FCA_J>,
       &launch_check_matrices<FCA_I, FCA_J>};
   return &set;
 }

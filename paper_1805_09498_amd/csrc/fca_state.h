@@ -75,6 +75,24 @@ struct AdjIter {
   float* xb;
 };
 
+// One checkpoint segment of the reverse pass in the tape (offsets in floats
+// from tape): the state before iteration j at slot j (slot 0 = ck, slot j > 0
+// at slot0 + j * stride), each state's v, lambda, P at v_off, lam_off,
+// P_off; the eq. 23 sums of iteration j at S + j * S_floats (S NULL:
+// recomputed); the adjoints of iterations len-1 .. 0 read buffer `cur` of
+// vb / lb / Pb first and alternate.
+struct AdjSeg {
+  const float* tape;
+  long long ck, slot0, stride, v_off, lam_off, P_off;
+  const float* S;
+  long long S_floats;
+  float* vb[2];
+  float* lb[2];
+  float2* Pb[2];
+  float* xb;
+  int len, cur;
+};
+
 // Where a recording run of the frequency-resident FastFCA-AS kernel writes
 // the state after each of its iterations: iteration it writes v, lambda and P
 // at offset it * stride (floats) from v / lam / P (the layouts of DevState),
@@ -110,6 +128,7 @@ struct KernelSet {
   hipError_t (*as_iter_resident_trace)(const DevState&, hipStream_t, int n_iter, int waves, int bpw,
                                        const Trace&);
   hipError_t (*adj_iter)(const DevState&, const AdjIter&, hipStream_t);
+  hipError_t (*adj_seg)(const DevState&, const AdjSeg&, hipStream_t);
   hipError_t (*adj_wiener)(const DevState&, const float2* gout, const AdjIter&, hipStream_t);
   hipError_t (*check_matrices)(const DevState&, hipStream_t, int em);  // P(f) / S_j(f), kFlagSingularParam
 };
