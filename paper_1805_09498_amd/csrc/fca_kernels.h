@@ -499,6 +499,117 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
   }
 }
 
+// The plain step at I >= 5: one wave per bin, lane (i, r) holding row r of
+// S_i.  The I lanes of a column's group factorise S_i = L L^H together
+// (right-looking Cholesky: the pivot and column k of L reach the group's
+// other lanes by lane shuffles), then solve L L^H a_i = N e_i by columns, so
+// that the dependent chain of one factorisation is spread over I lanes
+// instead of lying on one (k_as_solve).  Lane (i, r) then forms entry (r, i)
+// of P_new = P_old A.
+template <int I, int J>
+__global__ __launch_bounds__(kWave) void k_as_solve_rows(DevState s) {
+  static_assert(I * I <= kWave, "a bin's rows fit one wave");
+  const int f = blockIdx.x, lane = threadIdx.x;
+  const bool act = lane < I * I;
+  const int i = act ? lane / I : 0, r = act ? lane % I : 0;
+  const int base = i * I;  // the group's first lane
+  const float invN = 1.0f / float(s.N), fN = float(s.N);
+  __shared__ float sLr[I][I][I], sLi[I][I][I];  // [i][row][col] of L_i
+  // P_old row r, requested before the sums
+  float Por[I], Poi[I];
+#pragma unroll
+  for (int b = 0; b < I; ++b) {
+    const float2 p = s.P[(size_t)f * I * I + r * I + b];
+    Por[b] = p.x; Poi[b] = p.y;
+  }
+  // eq. 20
+  for (int t = lane; t < J * I; t += kWave) {
+    float* l = s.lam + (size_t)f * J * I + t;
+    *l = eq20_from_tiles<I, J>(s, f, t, *l, invN);
+  }
+  // row r of S_i from the tiles' packed sums (slot (a, b), a <= b: Re,
+  // (b, a), a < b: Im), each slot summed over the tiles in tile order
+  float Sr[I], Si[I];
+#pragma unroll
+  for (int c = 0; c < I; ++c) { Sr[c] = 0.f; Si[c] = 0.f; }
+  {
+    float ra[I], rb[I];
+#pragma unroll
+    for (int c = 0; c < I; ++c) { ra[c] = 0.f; rb[c] = 0.f; }
+#pragma unroll 4
+    for (int ch = 0; ch < s.nchunk; ++ch) {
+      const float* src = s.partB + ((size_t)f * s.nchunk + ch) * I * I * I + i * I * I;
+#pragma unroll
+      for (int c = 0; c < I; ++c) { ra[c] += src[r * I + c]; rb[c] += src[c * I + r]; }
+    }
+#pragma unroll
+    for (int c = 0; c < I; ++c) {
+      Sr[c] = (c >= r) ? ra[c] : rb[c];
+      Si[c] = (c > r) ? rb[c] : ((c < r) ? -ra[c] : 0.f);
+    }
+  }
+  // Cholesky: row r of the working matrix becomes row r of L
+  bool pd = true;
+  float dself = 1.f;  // 1 / L_rr
+#pragma unroll
+  for (int k = 0; k < I; ++k) {
+    const float skk = __shfl(Sr[k], base + k, kWave);
+    pd = pd && !(skk <= 0.f);
+    const float dk = sqrtT(skk > 1e-37f ? skk : 1e-37f);
+    const float ik = rcpT(dk);
+    if (r > k) { Sr[k] *= ik; Si[k] *= ik; }
+    if (r == k) { Sr[k] = dk; Si[k] = 0.f; dself = ik; }
+#pragma unroll
+    for (int c = k + 1; c < I; ++c) {
+      const float lr = __shfl(Sr[k], base + c, kWave), li = __shfl(Si[k], base + c, kWave);  // L_ck
+      if (r > k && c <= r) {  // S_rc -= L_rk conj(L_ck)
+        Sr[c] -= Sr[k] * lr + Si[k] * li;
+        Si[c] -= Si[k] * lr - Sr[k] * li;
+      }
+    }
+  }
+  if (act && r == 0 && !pd) atomicOr(s.flag, kFlagSingular);
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < I; ++c) { sLr[i][r][c] = Sr[c]; sLi[i][r][c] = Si[c]; }
+  }
+  // L z = N e_i, by columns: lane r accumulates N delta_ri - sum_k L_rk z_k
+  float zr = (r == i) ? fN : 0.f, zi = 0.f;
+#pragma unroll
+  for (int k = 0; k < I; ++k) {
+    if (r == k) { zr *= dself; zi *= dself; }
+    const float tr = __shfl(zr, base + k, kWave), ti = __shfl(zi, base + k, kWave);
+    if (r > k) {
+      zr -= Sr[k] * tr - Si[k] * ti;
+      zi -= Sr[k] * ti + Si[k] * tr;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();  // rows of L in LDS (one wave: in order)
+  // L^H a = z, by columns from the last: lane r subtracts conj(L_kr) a_k
+  float ar = zr, ai = zi;
+#pragma unroll
+  for (int k = I - 1; k >= 0; --k) {
+    if (r == k) { ar *= dself; ai *= dself; }
+    const float tr = __shfl(ar, base + k, kWave), ti = __shfl(ai, base + k, kWave);
+    if (r < k) {
+      const float lr = sLr[i][k][r], li = sLi[i][k][r];
+      ar -= lr * tr + li * ti;
+      ai -= lr * ti - li * tr;
+    }
+  }
+  // entry (r, i) of P_new = P_old A: a_i gathered from the group
+  float pr = 0.f, pi = 0.f;
+#pragma unroll
+  for (int b = 0; b < I; ++b) {
+    const float br = __shfl(ar, base + b, kWave), bi = __shfl(ai, base + b, kWave);
+    pr = fmaf(Por[b], br, pr);
+    pr = fmaf(-Poi[b], bi, pr);
+    pi = fmaf(Por[b], bi, pi);
+    pi = fmaf(Poi[b], br, pi);
+  }
+  if (act) s.P[(size_t)f * I * I + r * I + i] = make_float2(pr, pi);
+}
+
 template <int I, int J>
 hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
   dim3 grid(s.nchunk, s.F);
@@ -507,7 +618,14 @@ hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
   hipLaunchKernelGGL((k_as_pass_a<I, J>), grid, dim3(kBlock), 0, st, s);
   if (s.p_update != 4)
     hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
-  hipLaunchKernelGGL((k_as_solve<I, J>), dim3((s.F + 7) / 8), dim3(64), 0, st, s);
+  if constexpr (I >= 5) {
+    if (s.p_update == 0 && s.K == 1)
+      hipLaunchKernelGGL((k_as_solve_rows<I, J>), dim3(s.F), dim3(kWave), 0, st, s);
+    else
+      hipLaunchKernelGGL((k_as_solve<I, J>), dim3((s.F + 7) / 8), dim3(64), 0, st, s);
+  } else {
+    hipLaunchKernelGGL((k_as_solve<I, J>), dim3((s.F + 7) / 8), dim3(64), 0, st, s);
+  }
   if (s.p_update == 3) hipLaunchKernelGGL((k_as_newton<I, J>), dim3(s.F), dim3(kNewtonThreads), 0, st, s);
   if (s.p_update == 4) hipLaunchKernelGGL((k_as_emp_step<I, J>), dim3((s.F + 63) / 64), dim3(64), 0, st, s);
   return hipGetLastError();
