@@ -23,6 +23,8 @@
 // Further fixed-point steps (K > 1) iterate the same map on A from A = 1.
 #pragma once
 
+#include <type_traits>
+
 #include "fca_point.h"
 
 namespace fca {
@@ -117,6 +119,9 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
   // registers: there it would cost the second workgroup per CU).
   constexpr bool kKeepRd = kOnePass && NPT <= 8 && !kGen && !kTrace;
   float rdk[kKeepRd ? NPT : 1][I];
+  // The same kernels compile a second form of phases A and B for waves whose
+  // slots all hold frames (see phase_a).
+  constexpr bool kDense = kKeepRd;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tb + k * T;
@@ -157,6 +162,12 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       for (int i = 0; i < I; ++i) lam[j][i] = sLam[bin][j * I + i];
 
     // ---- phase A: E-step statistics, v update, eq. 20 summands ------------
+    // Issue priority: where the waves of two workgroups share a SIMD (the CU
+    // that holds an odd bin out, the batch kernels), the sections that every
+    // wave of a workgroup waits on -- the cross-wave sums, lambda, the
+    // per-bin solve -- issue ahead of the other workgroup's per-frame phases,
+    // which fill the gaps.  (One workgroup per CU: no effect.)
+    __builtin_amdgcn_s_setprio(0);
     {
       float S0[J], S1[J][I], lamI[J][I];
 #pragma unroll
@@ -165,9 +176,13 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 #pragma unroll
         for (int i = 0; i < I; ++i) { S1[j][i] = 0.f; lamI[j][i] = lam[j][i] * (1.0f / float(I)); }
       }
+      // every = true: all NPT slots of the wave hold frames, no slot is
+      // tested and the compiler interleaves the slots' dependency chains
+      // (one basic block); otherwise each slot is tested (wave-uniform).
+      auto phase_a = [&](auto every) {
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        if (wbase + k * T < s.N) {  // wave-uniform: skip slots no lane of the wave owns
+        if (decltype(every)::value || wbase + k * T < s.N) {
           const bool ok = tb + k * T < s.N;
           if constexpr (kXReg) {
             as_transform<I>(Pr, Pi, xr[k], xi[k], yr[k], yi[k]);
@@ -191,13 +206,12 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           float y2[I];
 #pragma unroll
           for (int i = 0; i < I; ++i) y2[i] = fmaf(yr[k][i], yr[k][i], yi[k][i] * yi[k][i]);
-          // a slot every lane of the wave owns skips the per-lane selects
           if constexpr (kKeepRd) {
-            if (wbase + k * T + kWave <= s.N)
-              as_point_em_rd<I, J>(y2, rdk[k], lamI, v[k], S0, S1, true);
-            else
-              as_point_em_rd<I, J>(y2, rdk[k], lamI, v[k], S0, S1, ok);
+            // one form for every slot: a copy without the per-lane selects
+            // for the full slots cost more in register copies than it saved
+            as_point_em_rd<I, J>(y2, rdk[k], lamI, v[k], S0, S1, ok);
           } else {
+            // a slot every lane of the wave owns skips the per-lane selects
             if (wbase + k * T + kWave <= s.N)
               as_point_em<I, J>(y2, lam, lamI, v[k], S0, S1, true);
             else
@@ -205,6 +219,11 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
           }
         }
       }
+      };
+      if (kDense && wbase + (NPT - 1) * T < s.N)
+        phase_a(std::true_type{});
+      else
+        phase_a(std::false_type{});
       float flat[kEq20Sums<I, J>];
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -212,6 +231,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
 #pragma unroll
         for (int i = 0; i < I; ++i) flat[J + j * I + i] = S1[j][i];
       }
+      __builtin_amdgcn_s_setprio(2);
       wave_totals_to_lds<kEq20Sums<I, J>>(flat, redS, VS);  // slot of wave `wave`
     }
     __syncthreads();
@@ -228,15 +248,17 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
     }
 
     // ---- phase B: the weighted sums N G_i of y y^H (eq. 23) ----------------
+    __builtin_amdgcn_s_setprio(0);
     if constexpr (kOnePass) {
       float A[I][I * I];
 #pragma unroll
       for (int i = 0; i < I; ++i)
 #pragma unroll
         for (int q = 0; q < I * I; ++q) A[i][q] = 0.f;
+      auto phase_b = [&](auto every) {
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        if (wbase + k * T < s.N) {
+        if (decltype(every)::value || wbase + k * T < s.N) {
           // lanes past N hold y = 0 and their initial v (kept by phase A), so
           // their weight is finite and they add nothing
           float w[I], z[I * I];
@@ -252,11 +274,17 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
             for (int q = 0; q < I * I; ++q) A[i][q] = fmaf(w[i], z[q], A[i][q]);
         }
       }
+      };
+      if (kDense && wbase + (NPT - 1) * T < s.N)
+        phase_b(std::true_type{});
+      else
+        phase_b(std::false_type{});
       float flat[I * I * I];
 #pragma unroll
       for (int i = 0; i < I; ++i)
 #pragma unroll
         for (int q = 0; q < I * I; ++q) flat[i * I * I + q] = A[i][q];
+      __builtin_amdgcn_s_setprio(2);
       wave_totals_to_lds<I * I * I>(flat, redQ, QSTRIDE);
     } else {
       // one pass over the points per CPP columns: a point's y y^H is formed
@@ -310,6 +338,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
       }
       }
     }
+    __builtin_amdgcn_s_setprio(2);
     __syncthreads();
 
     // ---- per-bin solve: lane c < I computes column c of eq. 23 ------------
@@ -322,6 +351,7 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
     // rotates with the iteration, so that on a CU whose SIMDs host waves of
     // two workgroups the serial solves land on every SIMD in turn.
     if (wl == (it & (nw - 1))) {  // nw is 1, 2 or 4
+      __builtin_amdgcn_s_setprio(3);  // every wave of the workgroup waits on this one
       // P_old for p_c = P_old a_c, requested before the solve's chain
       float Por[I][I], Poi[I][I];
 #pragma unroll
@@ -619,14 +649,24 @@ hipError_t launch_as_resident_g(const DevState& s, hipStream_t st, int n_iter, i
   const int need = (s.N + T - 1) / T;
   constexpr int mx = res_max_npt<I, J>();
   dim3 grid((s.F + bpw - 1) / bpw), block(waves * kWave);
-  if (need <= 4)
-    hipLaunchKernelGGL((k_as_resident<I, J, 4, kGen>), grid, block, 0, st, s, n_iter, bpw);
-  else if (need <= 8 && mx >= 8)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 8 ? 8 : 4), kGen>), grid, block, 0, st, s, n_iter, bpw);
-  else if (need <= 12 && mx >= 12)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 12 ? 12 : 4), kGen>), grid, block, 0, st, s, n_iter, bpw);
-  else if (need <= 16 && mx >= 16)
-    hipLaunchKernelGGL((k_as_resident<I, J, (mx >= 16 ? 16 : 4), kGen>), grid, block, 0, st, s, n_iter, bpw);
+  auto go = [&](auto npt) {
+    hipLaunchKernelGGL((k_as_resident<I, J, decltype(npt)::value, kGen>), grid, block, 0, st, s, n_iter, bpw);
+  };
+  // The plain step at I <= 4 takes the exact slot count below 8 (where the
+  // registers allow it), so that the waves of the full workgroups run the
+  // form of phases A and B without a test per slot.
+  constexpr bool kE = !kGen && I <= 4, kE8 = kE && mx >= 8;
+  using std::integral_constant;
+  if (kE && need == 1) go(integral_constant<int, kE ? 1 : 4>{});
+  else if (kE && need == 2) go(integral_constant<int, kE ? 2 : 4>{});
+  else if (kE && need == 3) go(integral_constant<int, kE ? 3 : 4>{});
+  else if (need <= 4) go(integral_constant<int, 4>{});
+  else if (kE8 && need == 5) go(integral_constant<int, kE8 ? 5 : 4>{});
+  else if (kE8 && need == 6) go(integral_constant<int, kE8 ? 6 : 4>{});
+  else if (kE8 && need == 7) go(integral_constant<int, kE8 ? 7 : 4>{});
+  else if (need <= 8 && mx >= 8) go(integral_constant<int, (mx >= 8 ? 8 : 4)>{});
+  else if (need <= 12 && mx >= 12) go(integral_constant<int, (mx >= 12 ? 12 : 4)>{});
+  else if (need <= 16 && mx >= 16) go(integral_constant<int, (mx >= 16 ? 16 : 4)>{});
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

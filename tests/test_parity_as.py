@@ -92,6 +92,23 @@ def test_resident_launch_shapes_agree(ff, waves, bpw):
     check_as_params(params(ff, ctx), ref, tag=f" w{waves}b{bpw}")
 
 
+@pytest.mark.parametrize("I,J,N", [(3, 3, 100), (3, 3, 200), (3, 3, 300), (3, 3, 600), (3, 3, 700), (3, 3, 850),
+                                   (2, 4, 250), (4, 2, 690)])
+def test_resident_exact_slot_counts(ff, I, J, N):
+    """The plain step at I <= 4 launches the kernel compiled for the exact
+    number of 64-frame slots per lane (4 waves, 2 bins: 128 lanes per bin, so
+    N = 100 .. 850 needs 1, 2, 3, 5, 6 and 7 slots).  Where every slot of a
+    wave holds frames the wave runs phases A and B without a test per slot
+    (both waves at N = 100, 200, 600, 850; one at 300, 700), elsewhere the
+    tested form; with F = 9 the last workgroup holds one bin on 4 waves (256
+    lanes) and takes the tested form.  Two iterations: the second E-step
+    starts from the weights kept by the first iteration's phase B."""
+    p = problem(I=I, J=J, F=9, N=N, seed=2100 + N)
+    ref = oracle_as_bounded(p, 2)
+    ctx = run_as(ff, p, 2, path=1, waves=4, bpw=2)
+    check_as_params(params(ff, ctx), ref, tag=f" I{I} J{J} N{N}")
+
+
 def test_inner_fixed_point_steps(ff):
     p = problem(3, 3, 33, 90, seed=5)
     ref = oracle_as_bounded(p, 1, K=3)
