@@ -175,7 +175,10 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * synchronises the stream.  0 = fixed preference order), "split_streams"
  * (FastFCA-AS on the streaming kernels: the bins are split into this many
  * parts, 1..4, default 2, that iterate on the context's stream and on
- * streams the library owns, forked and joined with events; 1 = one stream).  When the
+ * streams the library owns, forked and joined with events; 1 = one stream),
+ * "sums_mfma" (FastFCA-AS on the streaming kernels above I = 4: 1 = form
+ * the eq. 23 sums of pass B on the FP32 matrix cores, 0 = default, on the
+ * vector units, which measured faster; results agree to rounding).  When the
  * environment variable FASTFCA_TUNE_CACHE names a writable file, measured
  * shapes are also appended to it and read back by later processes (keyed by
  * GPU architecture, compute-unit count and library build; unreadable or
@@ -192,7 +195,7 @@ fca_status fca_set_option_f64(fca_ctx *ctx, const char *key, double value);
 fca_status fca_get_option_f64(fca_ctx *ctx, const char *key, double *value);
 
 /* Read an option ("K", "p_update", "check_finite", "path", "waves", "bins_per_wg",
- * "autotune", "split_streams": the configured values) or the launch shape the last iterate
+ * "autotune", "split_streams", "sums_mfma": the configured values) or the launch shape the last iterate
  * call used ("last_waves": waves per workgroup, 0 = streaming kernels, -1 =
  * no call yet; "last_bins_per_wg").  value is a host pointer.  Unknown keys
  * give FCA_ERR_ARG. */

@@ -114,6 +114,11 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
   __shared__ float sOut[J * I + 2 * I * I];
   __shared__ float red[adj_red_size<I, J>()];
 
+  // Issue priority: two or three workgroups share a CU, and the per-bin
+  // sections (set-up, solves, the block sums) that all waves of a workgroup
+  // wait on issue ahead of another workgroup's frame passes, which fill the
+  // gaps.
+  __builtin_amdgcn_s_setprio(2);
   const float* xf = s.xs + (size_t)f * 2 * I * Np;
   const float* vt = a.v_t + (size_t)f * J * Np;
   const float* vn = a.v_n + (size_t)f * J * Np;
@@ -178,6 +183,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
     float acc[I * I * I];
 #pragma unroll
     for (int k = 0; k < I * I * I; ++k) acc[k] = 0.f;
+    __builtin_amdgcn_s_setprio(0);  // frame pass
     for (int n = tid; n < N; n += kB) {
       int zo = 0;
       unsigned u = 4u * n;
@@ -194,6 +200,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
 #pragma unroll
         for (int k = 0; k < I * I; ++k) acc[i * I * I + k] = fmaf(w[i], z[k], acc[i * I * I + k]);
     }
+    __builtin_amdgcn_s_setprio(2);  // sums and per-bin work
     block_sum_t<I * I * I>(acc, &sS[0][0], red);
   } else {
 #pragma unroll 1
@@ -201,6 +208,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
       float acc[I * I];
 #pragma unroll
       for (int k = 0; k < I * I; ++k) acc[k] = 0.f;
+      __builtin_amdgcn_s_setprio(0);  // frame pass
       for (int n = tid; n < N; n += kB) {
         int zo = 0;
         unsigned u = 4u * n;
@@ -216,6 +224,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
         for (int k = 1; k < I; ++k) wi = (k == i) ? w[k] : wi;
         herm_rank1_acc<I>(acc, wi, yr, yi);
       }
+      __builtin_amdgcn_s_setprio(2);  // sums and per-bin work
       block_sum_t<I * I>(acc, &sS[i][0], red);
     }
   }
@@ -318,6 +327,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
     float acc[J * I];
 #pragma unroll
     for (int k = 0; k < J * I; ++k) acc[k] = 0.f;
+    __builtin_amdgcn_s_setprio(0);  // frame pass
     for (int n = tid; n < N; n += kB) {
       float xr[I], xi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I];
       if constexpr (kAdjPrefetch<I>) {
@@ -359,6 +369,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
       }
     }
     if (kAdjPrefetch<I> && tid < N) load2(tid, qxr, qxi, qvN, qv, qvb, qxbr, qxbi);  // first frame of pass 2
+    __builtin_amdgcn_s_setprio(2);  // sums and per-bin work
     block_sum_t<J * I>(acc, sLb, red);
     for (int t = tid; t < J * I; t += kB) sLm[t].z += sLb[t];
     __syncthreads();
@@ -369,6 +380,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
   float acc[J * I + 2 * I * I];  // lambda-bar sums, then sum_n x ybar^H (re, im)
 #pragma unroll
   for (int k = 0; k < J * I + 2 * I * I; ++k) acc[k] = 0.f;
+  __builtin_amdgcn_s_setprio(0);  // frame pass
   for (int n = tid; n < N; n += kB) {
     float xr[I], xi[I], yr[I], yi[I], vN[J], w[I], alr[I], ali[I], ber[I], bei[I], dpb[I], v[J], vb[J];
     float xbr[I], xbi[I];
@@ -517,6 +529,7 @@ __device__ __forceinline__ void adj_iter_body(const DevState& s, const AdjIter& 
       }
     }
   }
+  __builtin_amdgcn_s_setprio(2);  // sums and per-bin work
   block_sum_t<J * I + 2 * I * I>(acc, sOut, red);
   for (int t = tid; t < J * I; t += kB) a.lb_out[(size_t)f * J * I + t] = sOut[t];
   for (int t = tid; t < I * I; t += kB) {

@@ -207,13 +207,39 @@ struct PassBLayout {
   static_assert(kChunk % kThreads == 0, "stages tile a chunk");
 };
 
-template <int I, int J>
+// The matrix-core form of pass B's sums above I = 4 (option "sums_mfma";
+// the VALU form above is the default, being faster).  Each stage's frames
+// are staged in LDS as planes (plane q < I^2: entry q of the packed y y^H of
+// every frame of the stage; plane I^2 + c: the weight w_c), a frame per
+// column, and the stage's sums sum_n w_c(n) z_q(n) -- a contraction over the
+// frames, W^T Z with W = [w_c(n)] and Z = [z_q(n)] -- run on the FP32
+// 16x16x4 MFMA: rows c (I of the 16 used), 16 columns q per tile, 4 frames
+// per instruction, each of the two waves over its half of the stage's
+// frames.  A plane stride of 2 mod 32 words keeps both the writes (a frame
+// per lane) and the operand reads (lane (k, n): frame k, column n) on
+// distinct LDS banks; a last plane of zeros feeds the operand lanes past I
+// rows or I^2 columns.
+template <int I>
+struct PassBMfma {
+  static constexpr int kThreads = 128;                 // frames per stage: 2 waves
+  static constexpr int kStages = kChunk / kThreads;
+  static constexpr int kPlanes = I * I + I;            // then the zero plane
+  static constexpr int kPlane = kThreads + 2;
+  static constexpr int kNT = (I * I + 15) / 16;        // 16-column tiles of the I^2 sums
+  static constexpr int kFloats = (kPlanes + 1) * kPlane;
+  static_assert(kNT * 4 * kWave <= kPlanes * kPlane, "wave 1's partial sums reuse the planes");
+  static_assert(kChunk % kThreads == 0, "stages tile a chunk");
+};
+
+template <int I, int J, bool kMf = false>
 __global__ __launch_bounds__(PassBLayout<I>::kThreads) void k_as_pass_b(DevState s) {
   using L = PassBLayout<I>;
+  using M = PassBMfma<I>;
+  static_assert(!kMf || (L::kLds && L::kThreads == M::kThreads), "matrix-core form: above I = 4");
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float sLam[J * I];
   __shared__ float4 sPt[I * kPH<I>];
-  __shared__ float sRec[L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
+  __shared__ float sRec[kMf ? M::kFloats : L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
   const float invN = 1.0f / float(s.N);
   for (int t = threadIdx.x; t < J * I; t += L::kThreads)
     sLam[t] = eq20_from_tiles<I, J>(s, f, t, s.lam[(size_t)f * J * I + t], invN);  // eq. 20
@@ -268,6 +294,99 @@ __global__ __launch_bounds__(PassBLayout<I>::kThreads) void k_as_pass_b(DevState
 #pragma unroll
       for (int q = 0; q < I * I; ++q) flat[c * I * I + q] = A[c][q];
     block_totals_store<I * I * I>(flat, out, sRec);
+  } else if constexpr (kMf) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    constexpr int P = M::kPlane, NT = M::kNT;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int kq = lane >> 4, n16 = lane & 15;  // operand row k (frame of 4) and column n of a tile
+    for (int t = threadIdx.x; t < P; t += M::kThreads) sRec[M::kPlanes * P + t] = 0.f;  // the zero plane
+    v4f acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    float xr[I], xi[I], v[J], xrn[I], xin[I], vnx[J];
+    auto load = [&](int p) {
+      const int n = chunk * kChunk + p * M::kThreads + threadIdx.x;
+      const int nn = n < s.N ? n : 0;  // frames past N read frame 0 (weight 0)
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        xrn[i] = xf[(size_t)i * s.Npad + nn];
+        xin[i] = xf[(size_t)(I + i) * s.Npad + nn];
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) vnx[j] = vf[(size_t)j * s.Npad + nn];
+    };
+    load(0);
+    // operand offsets: A (lane: row n16 = c, frame kq) reads plane I^2 + c,
+    // B (lane: frame kq, column n16 of tile t) plane 16 t + n16; lanes past
+    // I (or I^2) read the zero plane
+    const int pa = ((n16 < I) ? I * I + n16 : M::kPlanes) * P;
+    int pb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) pb[t] = ((16 * t + n16 < I * I) ? 16 * t + n16 : M::kPlanes) * P;
+#pragma unroll 1
+    for (int p = 0; p < M::kStages; ++p) {
+#pragma unroll
+      for (int i = 0; i < I; ++i) { xr[i] = xrn[i]; xi[i] = xin[i]; }
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = vnx[j];
+      if (p + 1 < M::kStages) load(p + 1);
+      {
+        // this lane's frame: column threadIdx.x of every plane
+        const bool ok = chunk * kChunk + p * M::kThreads + (int)threadIdx.x < s.N;
+        int zo = 0;
+        asm volatile("" : "+s"(zo));
+        float yr[I], yi[I];
+        as_transform_lds<I>(sPt + zo, xr, xi, yr, yi);
+        float* col = sRec + threadIdx.x;
+#pragma unroll
+        for (int a2 = 0; a2 < I; ++a2) {
+          col[(a2 * I + a2) * P] = fmaf(yr[a2], yr[a2], yi[a2] * yi[a2]);
+#pragma unroll
+          for (int b = a2 + 1; b < I; ++b) {  // packed: Re at (a, b), Im at (b, a)
+            col[(a2 * I + b) * P] = fmaf(yr[a2], yr[b], yi[a2] * yi[b]);
+            col[(b * I + a2) * P] = fmaf(yi[a2], yr[b], -yr[a2] * yi[b]);
+          }
+        }
+        const float* lamz = sLam + zo;
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+          float d = v[0] * lamz[c];
+#pragma unroll
+          for (int j = 1; j < J; ++j) d = fmaf(v[j], lamz[j * I + c], d);
+          col[(I * I + c) * P] = ok ? rcp(d) : 0.f;
+        }
+      }
+      __syncthreads();
+      {
+        const float* fr = sRec + wv * kWave + kq;  // frame 64 wv + 4 st + kq: column fr + 4 st
+#pragma unroll 4
+        for (int st = 0; st < kWave / 4; ++st) {
+          const float a = fr[pa + 4 * st];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, fr[pb[t] + 4 * st], acc[t], 0, 0, 0);
+        }
+      }
+      __syncthreads();  // the planes are rewritten by the next stage
+    }
+    // the two waves' sums: wave 1 stores its tiles, wave 0 adds them and
+    // writes entry (c, q) = (4 kq + r, 16 t + n16) of the tile's sums
+    if (wv == 1) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sRec[(t * 4 + r) * kWave + lane] = acc[t][r];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = 4 * kq + r, q = 16 * t + n16;
+          if (c < I && q < I * I) out[c * I * I + q] = acc[t][r] + sRec[(t * 4 + r) * kWave + lane];
+        }
+    }
   } else {
     const int a = threadIdx.x % I, g = threadIdx.x / I;  // row a of group g (g >= kGroups: idle)
     float acc[I][I];                                     // [c][b]: row a, column b of S_c (packed)
@@ -616,8 +735,16 @@ hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
   // EM with P in the M-step: its sums need the v before pass A overwrites it
   if (s.p_update == 4) hipLaunchKernelGGL((k_as_pass_emp<I, J>), dim3(s.nchunk, s.F, J), dim3(kBlock), 0, st, s);
   hipLaunchKernelGGL((k_as_pass_a<I, J>), grid, dim3(kBlock), 0, st, s);
-  if (s.p_update != 4)
-    hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+  if (s.p_update != 4) {
+    if constexpr (I >= 5) {
+      if (s.sums_mfma)
+        hipLaunchKernelGGL((k_as_pass_b<I, J, true>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+      else
+        hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+    } else {
+      hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+    }
+  }
   if constexpr (I >= 5) {
     if (s.p_update == 0 && s.K == 1)
       hipLaunchKernelGGL((k_as_solve_rows<I, J>), dim3(s.F), dim3(kWave), 0, st, s);

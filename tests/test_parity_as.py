@@ -184,15 +184,21 @@ def test_deterministic(ff):
         np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("sums_mfma", [0, 1], ids=["valu", "mfma"])
 @pytest.mark.parametrize("I,J,seed,bins", [(8, 6, 3001, [0, 1, 137, 512, 800, 1024]),
                                            (6, 4, 3000, [0, 2, 250, 700, 1024])], ids=["long8x6", "long6x4"])
-def test_full_size_long_array_sampled_bins(ff, I, J, seed, bins):
+def test_full_size_long_array_sampled_bins(ff, I, J, seed, bins, sums_mfma):
     """The 60 s workloads (F=1025, N=3750, plane-wave + diffuse covariances,
     sparse log-normal spectra): one iteration on the whole problem in the
     launch configuration the benchmark uses, compared bin by bin on sampled
-    bins with the oracle run on those bins alone."""
+    bins with the oracle run on those bins alone; pass B's eq. 23 sums on the
+    vector units (the default) and on the matrix cores (option sums_mfma)."""
     p = problem(I, J, 1025, 3750, seed=seed, spatial="ula", psd="lognormal")
-    ctx = run_as(ff, p, 1)
+    t = to_dev(p)
+    ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])
+    ff.fca_set_option(ctx, "sums_mfma", sums_mfma)
+    assert ff.fca_get_option(ctx, "sums_mfma") == sums_mfma
+    ff.fastfca_as_iterate(ctx, 1)
     v, lam, P = params(ff, ctx)
     bins = np.array(bins)
     ref = oracle_as_bounded(sub_problem(p, bins), 1)
