@@ -121,6 +121,20 @@ def test_split_streams_same_bits(ff, I, J, F, N):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("I,J,F,N", [(8, 6, 5, 1100), (5, 3, 3, 3000)])
+def test_streaming_bin_solve_over_iterations(ff, I, J, F, N):
+    """Above I = 4: iterations one call at a time on the streaming path (2
+    and 3 tiles per bin, the last ragged; the bins split over two streams;
+    the row-parallel per-bin solve) against the oracle after each."""
+    p = problem(I, J, F, N, seed=700 + 10 * I + J)
+    ctx = run_as(ff, p, 0, path=2)
+    for it in range(3):
+        ff.fastfca_as_iterate(ctx, 1)
+        ref = oracle_as_bounded(p, it + 1)
+        check_as_params(params(ff, ctx), ref, tol=TOL_PARAM if it == 0 else None,
+                        tag=f" streaming solve I{I} it {it + 1}")
+
+
 @pytest.mark.parametrize("J", [1, 2, 3])
 def test_long_run_ragged_frames_stay_finite(ff, J):
     """Lanes past N (padding) must stay finite over long in-kernel runs: 300
