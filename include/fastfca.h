@@ -72,7 +72,10 @@ typedef enum {
 
 typedef enum {
   FCA_METHOD_AS = 0, /* FastFCA-AS: state (v, lambda, P), Section 4 */
-  FCA_METHOD_EM = 1  /* conventional FCA EM: state (v, S), Section 3.3 */
+  FCA_METHOD_EM = 1, /* conventional FCA EM: state (v, S), Section 3.3 */
+  /* not a method: widens the enum to every non-negative int, so that a
+   * caller's out-of-range value is a defined value the library rejects */
+  FCA_METHOD_MAX_ENUM = 0x7fffffff
 } fca_method;
 
 /* Create a context for one mixture (Section 2: estimate the J source images

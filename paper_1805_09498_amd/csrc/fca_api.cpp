@@ -430,7 +430,9 @@ fca_status validate_init(fca_method method, int F, int N, int I, int J, const vo
   if (N < I) return bad(FCA_ERR_ARG, "N must be at least I (the weighted covariances are singular otherwise)");
   const long long Npad = ((long long)N + 63) / 64 * 64;
   const int mx = I > J ? I : J;
-  if ((long long)F * Npad * 2 * mx >= (1LL << 31)) return bad(FCA_ERR_ARG, "problem too large (N*F*max(I,J) >= 2^31)");
+  // in double: exact below 2^53, and no overflow for any int arguments
+  if ((double)F * (double)Npad * 2.0 * mx >= 2147483648.0)
+    return bad(FCA_ERR_ARG, "problem too large (N*F*max(I,J) >= 2^31)");
   if (!x || !v0 || !lam0 || !P0) return bad(FCA_ERR_ARG, "x, v0, lam0 and P0 must be non-NULL device pointers");
   if (!aligned(x, 8) || !aligned(P0, 8) || !aligned(v0, 4) || !aligned(lam0, 4) || (R0 && !aligned(R0, 8)))
     return bad(FCA_ERR_ARG, "misaligned pointer (complex arrays need 8-byte, float arrays 4-byte alignment)");

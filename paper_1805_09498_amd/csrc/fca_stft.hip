@@ -140,7 +140,7 @@ fca_status fca_stft(const float* wav, int C, int L, int frame, int hop, fca_c64*
   check_frame(frame, hop, &lg);
   if (C < 1 || !wav || !X || !aligned(wav, 4) || !aligned(X, 8))
     return fca::ctx_fail(nullptr, FCA_ERR_ARG, "C must be positive; wav and X non-NULL, aligned device pointers");
-  if ((long long)F * N * C >= (1LL << 31) || (long long)C * L >= (1LL << 31))
+  if ((double)F * N * C >= 2147483648.0 || (double)C * L >= 2147483648.0)  // no overflow for any ints
     return fca::ctx_fail(nullptr, FCA_ERR_ARG, "signal too large");
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   const size_t lds = sizeof(float2) * (size_t)(frame + frame / 2);
@@ -159,7 +159,7 @@ fca_status fca_istft(const fca_c64* S, int J, int C, int N, int frame, int hop, 
   if (N != Nl) return fca::ctx_fail(nullptr, FCA_ERR_ARG, "N does not match the frame count of an L-sample signal");
   if (J < 1 || C < 1 || !S || !wav || !aligned(S, 8) || !aligned(wav, 4))
     return fca::ctx_fail(nullptr, FCA_ERR_ARG, "J, C must be positive; S and wav non-NULL, aligned device pointers");
-  if ((long long)J * C * N * frame >= (1LL << 31) || (long long)J * C * L >= (1LL << 31))
+  if ((double)J * C * N * frame >= 2147483648.0 || (double)J * C * L >= 2147483648.0)
     return fca::ctx_fail(nullptr, FCA_ERR_ARG, "signal too large");
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   float* frames = nullptr;
