@@ -42,6 +42,10 @@ __global__ __launch_bounds__(kResMaxBlock) void k_em_resident(DevState s, int n_
   const float invN = 1.0f / float(s.N);
 #pragma unroll 1
   for (int it = 0; it < n_iter; ++it) {
+    // issue priority as in k_as_resident: the per-point sums low, the
+    // cross-wave sums and the per-bin inversions (which every wave waits on)
+    // high, so that two workgroups sharing a CU fill each other's gaps
+    __builtin_amdgcn_s_setprio(0);
     float H[J][I * I];
 #pragma unroll
     for (int j = 0; j < J; ++j)
@@ -59,10 +63,12 @@ __global__ __launch_bounds__(kResMaxBlock) void k_em_resident(DevState s, int n_
     for (int j = 0; j < J; ++j)
 #pragma unroll
       for (int q = 0; q < I * I; ++q) flat[j * I * I + q] = H[j][q];
+    __builtin_amdgcn_s_setprio(2);
     wave_totals_to_lds<J * I * I>(flat, red, V);
     __syncthreads();
     // S_j <- (1/N) sum_n Rhat_j / v_j (eq. 10), and S_j^-1 for eq. 9.
     if (wbase == 0 && threadIdx.x < J) {
+      __builtin_amdgcn_s_setprio(3);
       const int j = threadIdx.x;
       float Rr[I][I], Ri[I][I], Xr[I][I], Xi[I][I];
       sum_waves<I * I>(red + j * I * I, V, nw, [&](int k, float t) {
