@@ -167,12 +167,24 @@ __global__ __launch_bounds__(kBlock) void k_as_pass_a(DevState s) {
 template <int I, int J>
 __device__ __forceinline__ float eq20_from_tiles(const DevState& s, int f, int t, float lam, float invN) {
   constexpr int V = kEq20Sums<I, J>;
+  const float* base = s.partA + (size_t)f * s.nchunk * V;
   float s0 = 0.f, s1 = 0.f;
-#pragma unroll 4
-  for (int c = 0; c < s.nchunk; ++c) {  // unrolled: the tiles' loads in flight together
-    const float* src = s.partA + ((size_t)f * s.nchunk + c) * V;
-    s0 += src[t / I];
-    s1 += src[J + t];
+  int c = 0;
+  // four tiles' values loaded before any is added (in flight together),
+  // then added in tile order
+  for (; c + 4 <= s.nchunk; c += 4) {
+    float l0[4], l1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      l0[u] = base[(size_t)(c + u) * V + t / I];
+      l1[u] = base[(size_t)(c + u) * V + J + t];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { s0 += l0[u]; s1 += l1[u]; }
+  }
+  for (; c < s.nchunk; ++c) {
+    s0 += base[(size_t)c * V + t / I];
+    s1 += base[(size_t)c * V + J + t];
   }
   return eq20_lambda(lam, s0, s1, invN);
 }
@@ -498,20 +510,37 @@ __global__ __launch_bounds__(64) void k_as_solve(DevState s) {
         const float2 t = s.P[(size_t)f * I * I + a * I + b];
         Pr[a][b] = t.x; Pi[a][b] = t.y;
       }
+    // S_i from the tile partials (EM with P in the M-step uses other sums),
+    // requested before the lambda stores below; four tiles' values loaded
+    // before any is added, then added in tile order
+    float A[I * I];
+#pragma unroll
+    for (int k = 0; k < I * I; ++k) A[k] = 0.f;
+    {
+      const int nc = s.p_update == 4 ? 0 : s.nchunk;
+      const float* base = s.partB + (size_t)f * s.nchunk * I * I * I + i * I * I;
+      int c = 0;
+      for (; c + 4 <= nc; c += 4) {
+        float l4[4][I * I];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < I * I; ++k) l4[u][k] = base[(size_t)(c + u) * I * I * I + k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < I * I; ++k) A[k] += l4[u][k];
+      }
+      for (; c < nc; ++c) {
+#pragma unroll
+        for (int k = 0; k < I * I; ++k) A[k] += base[(size_t)c * I * I * I + k];
+      }
+    }
     // lambda update (eq. 20): column i of every Lambda_j.
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       float* l = s.lam + (size_t)f * J * I + j * I + i;
       *l = eq20_from_tiles<I, J>(s, f, j * I + i, *l, invN);  // eq. 20
-    }
-    // S_i from the tile partials (EM with P in the M-step uses other sums).
-    float A[I * I];
-#pragma unroll
-    for (int k = 0; k < I * I; ++k) A[k] = 0.f;
-    for (int c = 0; c < (s.p_update == 4 ? 0 : s.nchunk); ++c) {
-      const float* src = s.partB + ((size_t)f * s.nchunk + c) * I * I * I + i * I * I;
-#pragma unroll
-      for (int k = 0; k < I * I; ++k) A[k] += src[k];
     }
     if (s.p_update == 3) {  // Newton's step: the totals go to the first tile's slot for k_as_newton
       float* dst = s.partB + (size_t)f * s.nchunk * I * I * I + i * I * I;
@@ -641,13 +670,11 @@ __global__ __launch_bounds__(kWave) void k_as_solve_rows(DevState s) {
     const float2 p = s.P[(size_t)f * I * I + r * I + b];
     Por[b] = p.x; Poi[b] = p.y;
   }
-  // eq. 20
-  for (int t = lane; t < J * I; t += kWave) {
-    float* l = s.lam + (size_t)f * J * I + t;
-    *l = eq20_from_tiles<I, J>(s, f, t, *l, invN);
-  }
   // row r of S_i from the tiles' packed sums (slot (a, b), a <= b: Re,
-  // (b, a), a < b: Im), each slot summed over the tiles in tile order
+  // (b, a), a < b: Im), each slot summed over the tiles in tile order.
+  // Requested before the eq. 20 update below, whose store to lambda the
+  // compiler would otherwise keep ahead of these loads (one more memory
+  // round trip on the solve's path).
   float Sr[I], Si[I];
 #pragma unroll
   for (int c = 0; c < I; ++c) { Sr[c] = 0.f; Si[c] = 0.f; }
@@ -655,9 +682,25 @@ __global__ __launch_bounds__(kWave) void k_as_solve_rows(DevState s) {
     float ra[I], rb[I];
 #pragma unroll
     for (int c = 0; c < I; ++c) { ra[c] = 0.f; rb[c] = 0.f; }
-#pragma unroll 4
-    for (int ch = 0; ch < s.nchunk; ++ch) {
-      const float* src = s.partB + ((size_t)f * s.nchunk + ch) * I * I * I + i * I * I;
+    const float* base = s.partB + (size_t)f * s.nchunk * I * I * I + i * I * I;
+    int ch = 0;
+    // four tiles' rows loaded before any is added (in flight together), then
+    // added in tile order
+    for (; ch + 4 <= s.nchunk; ch += 4) {
+      float la[4][I], lb[4][I];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* src = base + (size_t)(ch + u) * I * I * I;
+#pragma unroll
+        for (int c = 0; c < I; ++c) { la[u][c] = src[r * I + c]; lb[u][c] = src[c * I + r]; }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < I; ++c) { ra[c] += la[u][c]; rb[c] += lb[u][c]; }
+    }
+    for (; ch < s.nchunk; ++ch) {
+      const float* src = base + (size_t)ch * I * I * I;
 #pragma unroll
       for (int c = 0; c < I; ++c) { ra[c] += src[r * I + c]; rb[c] += src[c * I + r]; }
     }
@@ -666,6 +709,11 @@ __global__ __launch_bounds__(kWave) void k_as_solve_rows(DevState s) {
       Sr[c] = (c >= r) ? ra[c] : rb[c];
       Si[c] = (c > r) ? rb[c] : ((c < r) ? -ra[c] : 0.f);
     }
+  }
+  // eq. 20
+  for (int t = lane; t < J * I; t += kWave) {
+    float* l = s.lam + (size_t)f * J * I + t;
+    *l = eq20_from_tiles<I, J>(s, f, t, *l, invN);
   }
   // Cholesky: row r of the working matrix becomes row r of L
   bool pd = true;
