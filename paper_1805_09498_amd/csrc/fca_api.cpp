@@ -648,6 +648,15 @@ fca_status fca_set_params(fca_ctx* c, const float* v, const float* lam, const fc
   hipError_t e = hipSuccess;
   ++c->version;
   c->params_checked = 0;
+  if (v && c->method == FCA_METHOD_AS && (lam || P_or_R)) {
+    // v, lambda and P in one launch (a NULL lambda or P is skipped)
+    e = fca::launch_pack_v_copy2(v, s.vs, c->F, c->N, c->J, s.Npad, s.lam, lam,
+                                 lam ? (long long)c->F * c->J * c->I : 0, reinterpret_cast<float*>(s.P),
+                                 reinterpret_cast<const float*>(P_or_R), P_or_R ? 2LL * c->F * c->I * c->I : 0,
+                                 c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fca_set_params");
+    return FCA_OK;
+  }
   if (v) e = fca::launch_pack_v(v, s.vs, c->F, c->N, c->J, s.Npad, c->stream);
   if (e == hipSuccess && c->method == FCA_METHOD_AS && (lam || P_or_R)) {
     // lambda and P in one launch (a NULL one is skipped)

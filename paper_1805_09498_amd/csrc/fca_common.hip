@@ -65,6 +65,34 @@ __global__ void k_copy3(Copy3 c) {
   }
 }
 
+// A parameter reset in one launch: blockIdx.y = 0 packs v as k_pack_v does
+// (grid-stride over the F Npad frames), y = 1 and 2 copy lambda and P as
+// k_copy3 does (n = 0 skips an array).
+__global__ void k_pack_v_copy2(const float* __restrict__ v, float* __restrict__ vs, int F, int N, int J, int Npad,
+                               Copy3 c) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.y == 0) {
+    for (long long t = t0; t < (long long)F * Npad; t += stride) {
+      const int f = (int)(t / Npad), n = (int)(t % Npad);
+      for (int j = 0; j < J; ++j)
+        vs[((size_t)f * J + j) * Npad + n] = (n < N) ? v[((size_t)f * N + n) * J + j] : 1.f;
+    }
+    return;
+  }
+  const int a = blockIdx.y - 1;
+  float* d = c.dst[a];
+  const float* s = c.src[a];
+  const long long n = c.n[a];
+  if (((reinterpret_cast<unsigned long long>(d) | reinterpret_cast<unsigned long long>(s)) & 15) == 0) {
+    const long long n4 = n / 4;
+    for (long long i = t0; i < n4; i += stride) reinterpret_cast<float4*>(d)[i] = reinterpret_cast<const float4*>(s)[i];
+    for (long long i = n4 * 4 + t0; i < n; i += stride) d[i] = s[i];
+  } else {
+    for (long long i = t0; i < n; i += stride) d[i] = s[i];
+  }
+}
+
 __global__ void k_check_finite(const float* __restrict__ a, long long n, int* flag) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -134,6 +162,16 @@ hipError_t launch_copy3(float* d0, const float* s0, long long n0, float* d1, con
   long long bx = (mx / 4 + 255) / 256;
   bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
   hipLaunchKernelGGL(k_copy3, dim3((unsigned)bx, 3), dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_v_copy2(const float* v, float* vs, int F, int N, int J, int Npad, float* d1, const float* s1,
+                               long long n1, float* d2, const float* s2, long long n2, hipStream_t st) {
+  Copy3 c{{d1, d2, nullptr}, {s1, s2, nullptr}, {n1 > 0 ? n1 : 0, n2 > 0 ? n2 : 0, 0}};
+  const long long frames = (long long)F * Npad;
+  long long bx = (frames + 255) / 256;
+  bx = bx < 1 ? 1 : (bx > 4096 ? 4096 : bx);
+  hipLaunchKernelGGL(k_pack_v_copy2, dim3((unsigned)bx, 3), dim3(256), 0, st, v, vs, F, N, J, Npad, c);
   return hipGetLastError();
 }
 

@@ -42,6 +42,9 @@ namespace fca {
 // launch (fca_common.hip).
 hipError_t launch_copy3(float* d0, const float* s0, long long n0, float* d1, const float* s1, long long n1, float* d2,
                         const float* s2, long long n2, hipStream_t st);
+// v packed as launch_pack_v does, and two float arrays copied, in one launch
+hipError_t launch_pack_v_copy2(const float* v, float* vs, int F, int N, int J, int Npad, float* d1, const float* s1,
+                               long long n1, float* d2, const float* s2, long long n2, hipStream_t st);
 
 // Save the iterated state of a context to its backup region, or restore it.
 hipError_t copy_state(fca_ctx* c, bool save);
