@@ -120,8 +120,9 @@ __device__ __forceinline__ void as_resident_body(const DevState& s, int f0, int 
   constexpr bool kKeepRd = kOnePass && NPT <= 8 && !kGen && !kTrace;
   float rdk[kKeepRd ? NPT : 1][I];
   // The same kernels compile a second form of phases A and B for waves whose
-  // slots all hold frames (see phase_a).
-  constexpr bool kDense = kKeepRd;
+  // slots all hold frames (see phase_a); in the recording variant only up to
+  // 7 slots (at 8 its registers would leave one workgroup per CU).
+  constexpr bool kDense = kOnePass && !kGen && (kTrace ? NPT <= 7 : NPT <= 8);
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tb + k * T;
@@ -687,7 +688,19 @@ hipError_t launch_as_iter_resident_trace(const DevState& s, hipStream_t st, int 
   const int need = (s.N + T - 1) / T;
   constexpr int mx = res_max_npt<I, J>();
   dim3 grid((s.F + bpw - 1) / bpw), block(waves * kWave);
-  if (need <= 4)
+  auto go = [&](auto npt) {
+    hipLaunchKernelGGL((k_as_resident_trace<I, J, decltype(npt)::value>), grid, block, 0, st, s, n_iter, bpw, tr);
+  };
+  // exact slot counts below 8 at I <= 4, as the plain kernel's launcher
+  constexpr bool kE = I <= 4, kE8 = kE && mx >= 8;
+  using std::integral_constant;
+  if (kE && need == 1) go(integral_constant<int, kE ? 1 : 4>{});
+  else if (kE && need == 2) go(integral_constant<int, kE ? 2 : 4>{});
+  else if (kE && need == 3) go(integral_constant<int, kE ? 3 : 4>{});
+  else if (kE8 && need == 5) go(integral_constant<int, kE8 ? 5 : 4>{});
+  else if (kE8 && need == 6) go(integral_constant<int, kE8 ? 6 : 4>{});
+  else if (kE8 && need == 7) go(integral_constant<int, kE8 ? 7 : 4>{});
+  else if (need <= 4)
     hipLaunchKernelGGL((k_as_resident_trace<I, J, 4>), grid, block, 0, st, s, n_iter, bpw, tr);
   else if (need <= 8 && mx >= 8)
     hipLaunchKernelGGL((k_as_resident_trace<I, J, (mx >= 8 ? 8 : 4)>), grid, block, 0, st, s, n_iter, bpw, tr);
