@@ -134,6 +134,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline workload (no paper-shape, 60 s, batch legs)")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--stream-ceilings", action="store_true",
+                    help="print the GB/s of a 1.5 GB torch fill and copy, and exit")
     ap.add_argument("--batch", action="store_true",
                     help="uneven batch workload alone (64 mixtures, F=513, 30 iterations per step)")
     ap.add_argument("--graph", type=int, default=1)
@@ -153,6 +155,26 @@ def calibrate_copy():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "launches": 5}))
+
+
+def stream_ceilings():
+    """What plain torch streams reach on this GPU (HIP events, best of 5): a
+    1.5 GB write-only fill and a 1.5 GB copy -- the practical ceilings beside
+    the 8 TB/s peak for the output-bound Wiener filter."""
+    import torch
+    big = 3 << 29
+    x = torch.empty(big // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    rates = {}
+    for name, op, moved in (("fill_GBps", lambda: x.fill_(1.0), big), ("copy_GBps", lambda: y.copy_(x), 2 * big)):
+        best = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(); op(); e1.record(); torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        rates[name] = moved / (best * 1e-3) / 1e9
+    print(json.dumps({"stream_ceilings": rates}))
 
 
 # ---------------------------------------------------------------------------
@@ -476,6 +498,9 @@ def main():
         sys.exit(2)
     if args.batch:
         batch_main(args)
+        return
+    if args.stream_ceilings:
+        stream_ceilings()
         return
     if args.calibrate_copy:
         calibrate_copy()
