@@ -126,8 +126,9 @@ def parse():
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--split-streams", type=int, default=0,
                     help="streaming FastFCA-AS: streams the bins are split over (1..4; 0 = library default)")
-    ap.add_argument("--sums-mfma", type=int, default=0,
-                    help="streaming FastFCA-AS above I = 4: 1 = pass B's eq. 23 sums on the matrix cores")
+    ap.add_argument("--sums-mfma", type=int, default=-1,
+                    help="streaming FastFCA-AS above I = 4: pass B's eq. 23 sums on the vector units (0) or the "
+                         "matrix cores (1 = 16x16x4, 2 = 4x4x1 tiles); -1 = the library's default for I")
     ap.add_argument("--em-steps", type=int, default=3)
     ap.add_argument("--no-em", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -521,7 +522,7 @@ def main():
     opts = {"waves": args.waves, "bins_per_wg": args.bins_per_wg, "path": args.path, "autotune": args.autotune}
     if args.split_streams:
         opts["split_streams"] = args.split_streams
-    if args.sums_mfma:
+    if args.sums_mfma >= 0:
         opts["sums_mfma"] = args.sums_mfma
     ms_as, it_ms_as, L_as, shape_as = timed_job(ff, tens, ff.FCA_METHOD_AS, iters, args.steps, args.warmup, opts)
     pts = N * F * iters

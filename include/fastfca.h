@@ -179,9 +179,11 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * (FastFCA-AS on the streaming kernels: the bins are split into this many
  * parts, 1..4, default 2, that iterate on the context's stream and on
  * streams the library owns, forked and joined with events; 1 = one stream),
- * "sums_mfma" (FastFCA-AS on the streaming kernels above I = 4: 1 = form
- * the eq. 23 sums of pass B on the FP32 matrix cores, 0 = default, on the
- * vector units, which measured faster; results agree to rounding).  When the
+ * "sums_mfma" (FastFCA-AS on the streaming kernels above I = 4: where the
+ * eq. 23 sums of pass B run; 0 = vector units, 1 = FP32 matrix cores in
+ * 16x16x4 tiles, 2 = FP32 matrix cores in 16-block 4x4x1 tiles (I <= 8),
+ * -1 = default: 2 at I = 8, where it measured fastest, else 0; results
+ * agree to rounding).  When the
  * environment variable FASTFCA_TUNE_CACHE names a writable file, measured
  * shapes are also appended to it and read back by later processes (keyed by
  * GPU architecture, compute-unit count and library build; unreadable or

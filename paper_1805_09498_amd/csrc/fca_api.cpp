@@ -470,7 +470,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
 
   DevState& s = c->s;
   s.F = F; s.N = N; s.Npad = (int)Npad; s.K = 1;
-  s.p_update = 0; s.p_step = 0.1f; s.sums_mfma = 0;
+  s.p_update = 0; s.p_step = 0.1f; s.sums_mfma = -1;
   s.nchunk = (N + fca::kChunk - 1) / fca::kChunk;
   s.nchunk_em = (N + fca::kChunkEm - 1) / fca::kChunkEm;
   const size_t FJI = (size_t)F * J * I, FII = (size_t)F * I * I, FJII = (size_t)F * J * I * I;
@@ -705,7 +705,7 @@ fca_status fca_set_option(fca_ctx* c, const char* key, long long value) {
     if (value < 1 || value > 4) return fail(c, FCA_ERR_ARG, "split_streams must be in 1..4");
     c->split = (int)value;
   } else if (!std::strcmp(key, "sums_mfma")) {
-    if (value != 0 && value != 1) return fail(c, FCA_ERR_ARG, "sums_mfma must be 0 or 1");
+    if (value < -1 || value > 2) return fail(c, FCA_ERR_ARG, "sums_mfma must be -1, 0, 1 or 2");
     if (c->s.sums_mfma != (int)value) ++c->version;  // a recorded forward run no longer describes the iteration
     c->s.sums_mfma = (int)value;
   } else {

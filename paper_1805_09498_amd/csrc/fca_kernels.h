@@ -219,8 +219,8 @@ struct PassBLayout {
   static_assert(kChunk % kThreads == 0, "stages tile a chunk");
 };
 
-// The matrix-core form of pass B's sums above I = 4 (option "sums_mfma";
-// the VALU form above is the default, being faster).  Each stage's frames
+// The matrix-core form of pass B's sums above I = 4 (option "sums_mfma" = 1;
+// slower than the VALU form above at I = 6 and I = 8).  Each stage's frames
 // are staged in LDS as planes (plane q < I^2: entry q of the packed y y^H of
 // every frame of the stage; plane I^2 + c: the weight w_c), a frame per
 // column, and the stage's sums sum_n w_c(n) z_q(n) -- a contraction over the
@@ -243,15 +243,41 @@ struct PassBMfma {
   static_assert(kChunk % kThreads == 0, "stages tile a chunk");
 };
 
-template <int I, int J, bool kMf = false>
+// The same sums on the 16-block 4x4x1 FP32 MFMA (option "sums_mfma" = 2,
+// 5 <= I <= 8): block b of an instruction holds columns q = 4b .. 4b + 3
+// and rows c = 4h .. 4h + 3 (h = 0 .. ceil(I/4) - 1, an instruction each), one
+// frame per instruction, so lane l feeds plane q = l and the weight plane of
+// row 4h + l % 4, and every lane's column q is used while I^2 = 64.  Planes
+// are 16-byte aligned with a stride of 4 mod 32 words, so a lane's 128-bit
+// read of four consecutive frames and the eight lanes served together fall
+// on distinct banks.  Four accumulators per row group (one per frame of
+// four) keep each summation chain at the 16x16x4 form's length.
+template <int I>
+struct PassBMfma4 {
+  static constexpr int kThreads = 128;                 // frames per stage: 2 waves
+  static constexpr int kStages = kChunk / kThreads;
+  static constexpr int kPlanes = I * I + I;            // then the zero plane
+  static constexpr int kPlane = kThreads + 4;
+  static constexpr int kNH = (I + 3) / 4;              // row groups (instructions per frame)
+  static constexpr int kFloats = (kPlanes + 1) * kPlane;
+  static_assert(I * I <= kWave, "a lane per column q");
+  static_assert(kPlane % 32 == 4, "bank spread of the 128-bit operand reads");
+  static_assert(kNH * 4 * kWave <= kPlanes * kPlane, "wave 1's partial sums reuse the planes");
+  static_assert(kChunk % kThreads == 0, "stages tile a chunk");
+};
+
+template <int I, int J, int kMf = 0>
 __global__ __launch_bounds__(PassBLayout<I>::kThreads) void k_as_pass_b(DevState s) {
   using L = PassBLayout<I>;
   using M = PassBMfma<I>;
-  static_assert(!kMf || (L::kLds && L::kThreads == M::kThreads), "matrix-core form: above I = 4");
+  using M4 = PassBMfma4<I < 5 ? 5 : I>;
+  static_assert(kMf == 0 || (L::kLds && L::kThreads == M::kThreads && L::kThreads == M4::kThreads),
+                "matrix-core forms: above I = 4");
   const int f = blockIdx.y, chunk = blockIdx.x;
   __shared__ float sLam[J * I];
   __shared__ float4 sPt[I * kPH<I>];
-  __shared__ float sRec[kMf ? M::kFloats : L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
+  __shared__ __align__(16) float sRec[kMf == 2 ? M4::kFloats : kMf == 1 ? M::kFloats
+                                    : L::kLds ? L::kFloats : (kBlock / kWave) * pad4(I * I * I)];
   const float invN = 1.0f / float(s.N);
   for (int t = threadIdx.x; t < J * I; t += L::kThreads)
     sLam[t] = eq20_from_tiles<I, J>(s, f, t, s.lam[(size_t)f * J * I + t], invN);  // eq. 20
@@ -306,7 +332,110 @@ __global__ __launch_bounds__(PassBLayout<I>::kThreads) void k_as_pass_b(DevState
 #pragma unroll
       for (int q = 0; q < I * I; ++q) flat[c * I * I + q] = A[c][q];
     block_totals_store<I * I * I>(flat, out, sRec);
-  } else if constexpr (kMf) {
+  } else if constexpr (kMf == 2) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    constexpr int P = M4::kPlane, NH = M4::kNH;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (int t = threadIdx.x; t < P; t += M4::kThreads) sRec[M4::kPlanes * P + t] = 0.f;  // the zero plane
+    v4f acc[NH][4];
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[h][u] = v4f{0.f, 0.f, 0.f, 0.f};
+    float xr[I], xi[I], v[J], xrn[I], xin[I], vnx[J];
+    auto load = [&](int p) {
+      const int n = chunk * kChunk + p * M4::kThreads + threadIdx.x;
+      const int nn = n < s.N ? n : 0;  // frames past N read frame 0 (weight 0)
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        xrn[i] = xf[(size_t)i * s.Npad + nn];
+        xin[i] = xf[(size_t)(I + i) * s.Npad + nn];
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) vnx[j] = vf[(size_t)j * s.Npad + nn];
+    };
+    load(0);
+    // operand planes: B (lane l: column q = l) and A of row group h (lane l:
+    // row 4h + l % 4); lanes past I^2 columns or I rows read the zero plane
+    const int pb = (lane < I * I ? lane : M4::kPlanes) * P;
+    int pa[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) pa[h] = (4 * h + (lane & 3) < I ? I * I + 4 * h + (lane & 3) : M4::kPlanes) * P;
+#pragma unroll 1
+    for (int p = 0; p < M4::kStages; ++p) {
+#pragma unroll
+      for (int i = 0; i < I; ++i) { xr[i] = xrn[i]; xi[i] = xin[i]; }
+#pragma unroll
+      for (int j = 0; j < J; ++j) v[j] = vnx[j];
+      if (p + 1 < M4::kStages) load(p + 1);
+      {
+        // this lane's frame: column threadIdx.x of every plane
+        const bool ok = chunk * kChunk + p * M4::kThreads + (int)threadIdx.x < s.N;
+        int zo = 0;
+        asm volatile("" : "+s"(zo));
+        float yr[I], yi[I];
+        as_transform_lds<I>(sPt + zo, xr, xi, yr, yi);
+        float* col = sRec + threadIdx.x;
+#pragma unroll
+        for (int a2 = 0; a2 < I; ++a2) {
+          col[(a2 * I + a2) * P] = fmaf(yr[a2], yr[a2], yi[a2] * yi[a2]);
+#pragma unroll
+          for (int b = a2 + 1; b < I; ++b) {  // packed: Re at (a, b), Im at (b, a)
+            col[(a2 * I + b) * P] = fmaf(yr[a2], yr[b], yi[a2] * yi[b]);
+            col[(b * I + a2) * P] = fmaf(yi[a2], yr[b], -yr[a2] * yi[b]);
+          }
+        }
+        const float* lamz = sLam + zo;
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+          float d = v[0] * lamz[c];
+#pragma unroll
+          for (int j = 1; j < J; ++j) d = fmaf(v[j], lamz[j * I + c], d);
+          col[(I * I + c) * P] = ok ? rcp(d) : 0.f;
+        }
+      }
+      __syncthreads();
+      {
+        const float* fr = sRec + wv * kWave;  // this wave's 64 frames of the stage
+#pragma unroll 4
+        for (int st = 0; st < kWave / 4; ++st) {
+          const float4 b4 = *reinterpret_cast<const float4*>(fr + pb + 4 * st);
+          float4 a4[NH];
+#pragma unroll
+          for (int h = 0; h < NH; ++h) a4[h] = *reinterpret_cast<const float4*>(fr + pa[h] + 4 * st);
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            acc[h][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[h].x, b4.x, acc[h][0], 0, 0, 0);
+            acc[h][1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[h].y, b4.y, acc[h][1], 0, 0, 0);
+            acc[h][2] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[h].z, b4.z, acc[h][2], 0, 0, 0);
+            acc[h][3] = __builtin_amdgcn_mfma_f32_4x4x1f32(a4[h].w, b4.w, acc[h][3], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();  // the planes are rewritten by the next stage
+    }
+    // lane l holds, in register r of row group h, the sum for (c, q) =
+    // (4h + r, l); wave 1 stores its sums, wave 0 adds them and writes
+    v4f tot[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) tot[h] = (acc[h][0] + acc[h][1]) + (acc[h][2] + acc[h][3]);
+    if (wv == 1) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sRec[(h * 4 + r) * kWave + lane] = tot[h][r];
+    }
+    __syncthreads();
+    if (wv == 0 && lane < I * I) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = 4 * h + r;
+          if (c < I) out[c * I * I + lane] = tot[h][r] + sRec[(h * 4 + r) * kWave + lane];
+        }
+    }
+  } else if constexpr (kMf == 1) {
     typedef float v4f __attribute__((ext_vector_type(4)));
     constexpr int P = M::kPlane, NT = M::kNT;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -785,8 +914,12 @@ hipError_t launch_as_iter_stream(const DevState& s, hipStream_t st) {
   hipLaunchKernelGGL((k_as_pass_a<I, J>), grid, dim3(kBlock), 0, st, s);
   if (s.p_update != 4) {
     if constexpr (I >= 5) {
-      if (s.sums_mfma)
-        hipLaunchKernelGGL((k_as_pass_b<I, J, true>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+      // default (-1): the 4x4x1 matrix-core form where it measured faster (I = 8)
+      const int form = s.sums_mfma < 0 ? (I == 8 ? 2 : 0) : s.sums_mfma;
+      if (form == 2 && I <= 8)
+        hipLaunchKernelGGL((k_as_pass_b<I, J, (I <= 8 ? 2 : 1)>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
+      else if (form == 1)
+        hipLaunchKernelGGL((k_as_pass_b<I, J, 1>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
       else
         hipLaunchKernelGGL((k_as_pass_b<I, J>), grid, dim3(PassBLayout<I>::kThreads), 0, st, s);
     } else {

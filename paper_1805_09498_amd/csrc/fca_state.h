@@ -41,7 +41,7 @@ struct DevState {
   int p_update;   // P step: 0 fixed point (eq. 23), 1 gradient, 2 natural gradient, 3 Newton,
                   // 4 EM with P in the M-step
   float p_step;   // step size of the gradient-type P steps
-  int sums_mfma;  // streaming pass B above I = 4: eq. 23 sums on the matrix cores (0: VALU)
+  int sums_mfma;  // streaming pass B above I = 4: eq. 23 sums, 0 VALU, 1 / 2 matrix-core tiles, -1 by I
   const float* xs;
   float* vs;
   float* lam;

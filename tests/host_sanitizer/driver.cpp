@@ -76,7 +76,7 @@ static void options() {
       {"bins_per_wg", 2, FCA_OK}, {"bins_per_wg", 3, FCA_ERR_ARG},
       {"autotune", 0, FCA_OK}, {"autotune", 2, FCA_ERR_ARG},
       {"split_streams", 4, FCA_OK}, {"split_streams", 0, FCA_ERR_ARG}, {"split_streams", 5, FCA_ERR_ARG},
-      {"sums_mfma", 1, FCA_OK}, {"sums_mfma", 2, FCA_ERR_ARG},
+      {"sums_mfma", 2, FCA_OK}, {"sums_mfma", 1, FCA_OK}, {"sums_mfma", 3, FCA_ERR_ARG}, {"sums_mfma", -2, FCA_ERR_ARG},
       {"", 1, FCA_ERR_ARG}, {"no such option", 1, FCA_ERR_ARG}, {"Kx", 1, FCA_ERR_ARG},
   };
   for (const Opt& o : set) {

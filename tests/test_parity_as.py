@@ -184,7 +184,7 @@ def test_deterministic(ff):
         np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("sums_mfma", [0, 1], ids=["valu", "mfma"])
+@pytest.mark.parametrize("sums_mfma", [0, 1, 2], ids=["valu", "mfma16x16x4", "mfma4x4x1"])
 @pytest.mark.parametrize("I,J,seed,bins", [(8, 6, 3001, [0, 1, 137, 512, 800, 1024]),
                                            (6, 4, 3000, [0, 2, 250, 700, 1024])], ids=["long8x6", "long6x4"])
 def test_full_size_long_array_sampled_bins(ff, I, J, seed, bins, sums_mfma):
@@ -192,7 +192,8 @@ def test_full_size_long_array_sampled_bins(ff, I, J, seed, bins, sums_mfma):
     sparse log-normal spectra): one iteration on the whole problem in the
     launch configuration the benchmark uses, compared bin by bin on sampled
     bins with the oracle run on those bins alone; pass B's eq. 23 sums on the
-    vector units (the default) and on the matrix cores (option sums_mfma)."""
+    vector units (the default) and on the matrix cores in both tile forms
+    (option sums_mfma)."""
     p = problem(I, J, 1025, 3750, seed=seed, spatial="ula", psd="lognormal")
     t = to_dev(p)
     ctx = ff.fca_init(ff.FCA_METHOD_AS, t["x"], t["v0"], t["lam0"], t["P0"])

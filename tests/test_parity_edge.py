@@ -135,6 +135,22 @@ def test_streaming_bin_solve_over_iterations(ff, I, J, F, N):
                         tag=f" streaming solve I{I} it {it + 1}")
 
 
+@pytest.mark.parametrize("sums_mfma", [1, 2], ids=["mfma16x16x4", "mfma4x4x1"])
+@pytest.mark.parametrize("I,J", [(5, 2), (6, 4), (7, 3), (8, 6)])
+def test_streaming_sums_on_matrix_cores(ff, I, J, sums_mfma):
+    """Pass B's eq. 23 sums on the matrix cores (both tile forms) at every I
+    they serve: two tiles per bin, the second ragged, two iterations one call
+    at a time against the oracle."""
+    p = problem(I, J, 4, 1100, seed=900 + 10 * I + J)
+    ctx = run_as(ff, p, 0, path=2)
+    ff.fca_set_option(ctx, "sums_mfma", sums_mfma)
+    for it in range(2):
+        ff.fastfca_as_iterate(ctx, 1)
+        ref = oracle_as_bounded(p, it + 1)
+        check_as_params(params(ff, ctx), ref, tol=TOL_PARAM if it == 0 else None,
+                        tag=f" sums_mfma {sums_mfma} I{I}J{J} it {it + 1}")
+
+
 @pytest.mark.parametrize("J", [1, 2, 3])
 def test_long_run_ragged_frames_stay_finite(ff, J):
     """Lanes past N (padding) must stay finite over long in-kernel runs: 300
