@@ -177,7 +177,7 @@ fca_status fca_set_params(fca_ctx *ctx, const float *v, const float *lam,
  * caches the fastest for the process under (method, I, J, F, N, K); this call
  * synchronises the stream.  0 = fixed preference order), "split_streams"
  * (FastFCA-AS on the streaming kernels: the bins are split into this many
- * parts, 1..4, default 2, that iterate on the context's stream and on
+ * parts, 1..4, default 3, that iterate on the context's stream and on
  * streams the library owns, forked and joined with events; 1 = one stream),
  * "sums_mfma" (FastFCA-AS on the streaming kernels above I = 4: where the
  * eq. 23 sums of pass B run; 0 = vector units, 1 = FP32 matrix cores in

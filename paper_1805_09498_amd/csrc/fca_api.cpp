@@ -462,7 +462,7 @@ fca_status fca_init(fca_ctx** out, fca_method method, int F, int N, int I, int J
   c->method = method; c->F = F; c->N = N; c->I = I; c->J = J;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ks = ks; c->check_finite = 0; c->params_checked = 0; c->path = 0; c->waves = 0; c->bpw = 0; c->autotune = 1;
-  c->split = 2; c->ev_fork = nullptr;
+  c->split = 3; c->ev_fork = nullptr;
   for (int k = 0; k < 3; ++k) { c->side[k] = nullptr; c->ev_join[k] = nullptr; }
   c->backup = nullptr; c->arena = nullptr; c->last_waves = -1; c->last_bpw = -1;
   c->version = 0; c->tape = nullptr; c->tape_bytes = 0; c->tape_iters = 0; c->tape_every = 0;
